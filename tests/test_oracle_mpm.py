@@ -1,0 +1,300 @@
+"""Pins of the oracle MLS-MPM substep (no GPU).
+
+- P2G conserves mass and momentum exactly (quadratic B-spline weights sum to
+  one and have zero first moment), checked to 1e-12 relative.
+- P2G and G2P agree with a brute-force sum over every grid node using the
+  B-spline kernel N(r) = 3/4 - r^2 (|r| < 1/2), (3/2 - |r|)^2 / 2
+  (1/2 <= |r| < 3/2) on 16-particle scenes.
+- G2P reproduces an affine grid velocity field exactly (v and C).
+- Fixed-corotated stress: tau(I) = 0, tau(R) = 0, and tau = (dpsi/dF) F^T
+  against central finite differences of psi; the polar factor equals
+  scipy.linalg.polar's.
+- Config c1 (2D block at rest, round to nearest) has a closed form under the
+  quantized-state model of Eq. 1: u_v drops 2 LSB every step, the y position
+  code drops round(0.128 (k-1) + 0.10276...) at step k, C and F keep the
+  codes of 0 and I.  This is the systematic bias of Fig. 4 / Fig. 5 written
+  out.  With dither the mean velocity follows -n g dt.
+- Resume: 25 + 25 steps equal 50 steps bit for bit.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import workloads as WL
+
+
+def N1(r):
+    r = np.abs(r)
+    return np.where(r < 0.5, 0.75 - r * r, np.where(r < 1.5, 0.5 * (1.5 - r) ** 2, 0.0))
+
+
+def small_scene(rng, dim, n=16, res=16):
+    x = rng.uniform(0.3, 0.7, (dim, n))
+    v = rng.standard_normal((dim, n))
+    C = rng.standard_normal((dim * dim, n))
+    F = np.zeros((dim * dim, n))
+    for a in range(dim):
+        F[a * dim + a] = 1.0
+    F += 0.1 * rng.standard_normal((dim * dim, n))
+    p = WL.params(dim, res, 1e-3, 1.0 / res ** dim / 4)
+    return p, x, v, C, F
+
+
+def node_positions(dim, res):
+    g = np.arange(res) / res
+    if dim == 2:
+        X, Y = np.meshgrid(g, g, indexing="xy")
+        return np.stack([X.ravel(), Y.ravel()])
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p2g_conservation(orc, dim):
+    rng = np.random.default_rng(0)
+    p, x, v, C, F = small_scene(rng, dim, n=500, res=32)
+    gm, gmom = orc.p2g(p, x, v, C, F)
+    m_p = p["rho"] * p["p_vol"]
+    assert abs(gm.sum() - m_p * x.shape[1]) <= 1e-12 * m_p * x.shape[1]
+    for a in range(dim):
+        total = m_p * v[a].sum()
+        assert abs(gmom[a].sum() - total) <= 1e-12 * m_p * np.abs(v[a]).sum()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p2g_brute_force(orc, dim):
+    rng = np.random.default_rng(1)
+    p, x, v, C, F = small_scene(rng, dim)
+    res = p["grid_res"]
+    dx = 1.0 / res
+    gm, gmom = orc.p2g(p, x, v, C, F)
+    xi = node_positions(dim, res)
+    m_p = p["rho"] * p["p_vol"]
+    mu = p["E"] / (2 * (1 + p["nu"]))
+    la = p["E"] * p["nu"] / ((1 + p["nu"]) * (1 - 2 * p["nu"]))
+    bm = np.zeros(xi.shape[1])
+    bmom = np.zeros((dim, xi.shape[1]))
+    for q in range(x.shape[1]):
+        Fq = F[:, q].reshape(dim, dim)
+        tau = orc.kirchhoff(Fq, mu, la)  # pinned on its own below
+        A = -p["dt"] * p["p_vol"] * 4 / dx ** 2 * tau + m_p * C[:, q].reshape(dim, dim)
+        d = xi - x[:, q:q + 1]
+        w = np.prod(N1(d / dx), axis=0)
+        bm += w * m_p
+        bmom += w * (m_p * v[:, q:q + 1] + A @ d)
+    assert np.allclose(gm, bm, rtol=1e-12, atol=1e-15)
+    assert np.allclose(gmom, bmom, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_g2p_brute_force(orc, dim):
+    rng = np.random.default_rng(2)
+    p, x, v, C, F = small_scene(rng, dim)
+    res = p["grid_res"]
+    dx = 1.0 / res
+    gv = rng.standard_normal((dim, res ** dim))
+    x1, v1, C1, F1 = orc.g2p(p, x, F, gv)
+    xi = node_positions(dim, res)
+    for q in range(x.shape[1]):
+        d = xi - x[:, q:q + 1]
+        w = np.prod(N1(d / dx), axis=0)
+        vq = (w * gv).sum(axis=1)
+        Cq = 4 / dx ** 2 * (w * gv) @ d.T
+        assert np.allclose(v1[:, q], vq, rtol=1e-12, atol=1e-13)
+        assert np.allclose(C1[:, q].reshape(dim, dim), Cq, rtol=1e-11, atol=1e-10)
+        assert np.allclose(x1[:, q], x[:, q] + p["dt"] * vq, rtol=0, atol=1e-15)
+        Fn = (np.eye(dim) + p["dt"] * Cq) @ F[:, q].reshape(dim, dim)
+        assert np.allclose(F1[:, q].reshape(dim, dim), Fn, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_g2p_affine_reproduction(orc, dim):
+    rng = np.random.default_rng(3)
+    p, x, v, C, F = small_scene(rng, dim, n=64, res=32)
+    a = rng.standard_normal(dim)
+    B = rng.standard_normal((dim, dim))
+    xi = node_positions(dim, p["grid_res"])
+    gv = a[:, None] + B @ xi
+    x1, v1, C1, _ = orc.g2p(p, x, F, gv)
+    assert np.allclose(v1, a[:, None] + B @ x, atol=1e-12)
+    assert np.allclose(C1, np.repeat(B.reshape(-1, 1), x.shape[1], axis=1), atol=1e-10)
+
+
+def psi(F, mu, la):
+    U, s, Vt = np.linalg.svd(F)
+    R = U @ Vt
+    if np.linalg.det(R) < 0:
+        U[:, -1] *= -1
+        R = U @ Vt
+    J = np.linalg.det(F)
+    return mu * np.sum((F - R) ** 2) + 0.5 * la * (J - 1) ** 2
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_stress(orc, dim):
+    rng = np.random.default_rng(4)
+    mu, la = 416.6666666666667, 277.77777777777777
+    assert np.allclose(orc.kirchhoff(np.eye(dim), mu, la), 0, atol=1e-12)
+    for _ in range(10):
+        Q, _ = np.linalg.qr(rng.standard_normal((dim, dim)))
+        if np.linalg.det(Q) < 0:
+            Q[:, 0] *= -1
+        assert np.allclose(orc.kirchhoff(Q, mu, la), 0, atol=1e-9)
+        F = np.eye(dim) + 0.3 * rng.standard_normal((dim, dim))
+        if np.linalg.det(F) <= 0.1:
+            continue
+        tau = orc.kirchhoff(F, mu, la)
+        h = 1e-6
+        P = np.zeros((dim, dim))
+        for i in range(dim):
+            for j in range(dim):
+                Fp = F.copy(); Fp[i, j] += h
+                Fm = F.copy(); Fm[i, j] -= h
+                P[i, j] = (psi(Fp, mu, la) - psi(Fm, mu, la)) / (2 * h)
+        assert np.allclose(tau, P @ F.T, rtol=1e-6, atol=1e-5)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_polar_matches_scipy(orc, dim):
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        F = np.eye(dim) + 0.5 * rng.standard_normal((dim, dim))
+        if np.linalg.det(F) <= 1e-3:
+            continue
+        R = orc.polar(F)
+        Rs, _ = scipy.linalg.polar(F)
+        assert np.allclose(R, Rs, atol=1e-10)
+        assert np.allclose(R @ R.T, np.eye(dim), atol=1e-12)
+    # reflected F: nearest rotation (det +1), singular F handled
+    F = np.diag([1.0, 1.0, -0.5])[:dim, :dim] if dim == 3 else np.diag([1.0, -0.5])
+    R = orc.polar(F)
+    assert np.isclose(np.linalg.det(R), 1.0)
+    R0 = orc.polar(np.zeros((dim, dim)))
+    assert np.allclose(R0, np.eye(dim))
+
+
+def test_grid_update_gravity_and_walls(orc):
+    p = WL.params(2, 16, 1e-3, 1e-4)
+    n = 16 * 16
+    gm = np.ones(n)
+    gm[5] = 0.0
+    gmom = np.zeros((2, n))
+    gmom[0] = -1.0  # moving left everywhere
+    gv = orc.grid_update(p, gm, gmom)
+    i = np.arange(n) % 16
+    j = np.arange(n) // 16
+    assert np.all(gv[:, 5] == 0)
+    mask = gm > 0
+    assert np.all(gv[0][mask & (i < 3)] == 0)
+    assert np.allclose(gv[0][mask & (i >= 3)], -1.0)
+    vy = -9.8e-3
+    assert np.all(gv[1][mask & (j < 3)] == 0)
+    assert np.allclose(gv[1][mask & (j >= 3)], vy)
+
+
+# ------------------------------------------------------------------ config c1
+def c1_closed_form(words0, steps, orc, scheme):
+    """Expected packed codes of c1 after `steps` steps, per original particle."""
+    dv = 40.0 / 2 ** 16
+    dxq = 2.0 ** -20
+    g, dt = 9.8, 1e-4
+    drop = 0
+    for k in range(1, steps + 1):
+        t = (2 * (k - 1) * dv + g * dt) * dt / dxq
+        frac = t - np.floor(t)
+        assert abs(frac - 0.5) > 1e-3  # every rounding decision has a margin
+        drop += int(np.floor(t + 0.5))
+    return 32768 - 2 * steps, drop
+
+
+def codes_of(orc, scheme, words, field, comp):
+    comps, _, _, _ = orc.layout(scheme)
+    f = [f for f in scheme["fields"] if f["field"] == field][0]
+    off = int(comps["xvCF".index(field), comp])
+    w = words.astype(np.uint64)
+    lo = w[off // 32]
+    hi = w[off // 32 + 1] if off // 32 + 1 < w.shape[0] else np.zeros_like(lo)
+    both = lo | (hi << np.uint64(32))
+    return ((both >> np.uint64(off % 32)) & np.uint64((1 << f["bits"]) - 1)).astype(np.int64)
+
+
+def test_c1_closed_form_bit_exact(orc):
+    sc = WL.c1()
+    x, v, C, F = sc["state"]
+    words0, _ = orc.encode(sc["scheme"], x, v, C, F, 0, 2)
+    sim = orc.Sim(sc["scheme"], sc["params"], words0)
+    sim.step(50)
+    w = sim.words()
+    ids = sim.ids()
+    uv, drop = c1_closed_form(words0, 50, orc, sc["scheme"])
+    assert drop == 161
+    s = sc["scheme"]
+    assert np.all(codes_of(orc, s, w, "v", 1) == uv)
+    assert np.all(codes_of(orc, s, w, "v", 0) == 32768)
+    assert np.array_equal(codes_of(orc, s, w, "x", 0), codes_of(orc, s, words0, "x", 0)[ids])
+    assert np.array_equal(codes_of(orc, s, w, "x", 1), codes_of(orc, s, words0, "x", 1)[ids] - drop)
+    for c in range(4):
+        assert np.all(codes_of(orc, s, w, "C", c) == 32768)
+        assert np.all(codes_of(orc, s, w, "F", c) == 32768)
+    _, vq, _, _ = orc.decode(s, w)
+    assert np.allclose(vq[1], -0.06103515625)
+
+
+def test_resume_bit_exact(orc):
+    sc = WL.c1()
+    sc["scheme"] = WL.scheme_c1(2, True, 7)
+    sc["params"]["sort_every"] = 8
+    x, v, C, F = sc["state"]
+    words0, _ = orc.encode(sc["scheme"], x, v, C, F, 0, 2)
+    a = orc.Sim(sc["scheme"], sc["params"], words0)
+    a.step(50)
+    b = orc.Sim(sc["scheme"], sc["params"], words0)
+    b.step(25)
+    b.step(25)
+    assert np.array_equal(a.words(), b.words())
+    assert np.array_equal(a.ids(), b.ids())
+
+
+def test_dithered_free_fall_unbiased(orc):
+    sc = WL.c1()
+    sc["scheme"] = WL.scheme_c1(2, True, 3)
+    x, v, C, F = sc["state"]
+    words0, _ = orc.encode(sc["scheme"], x, v, C, F, 0, 2)
+    sim = orc.Sim(sc["scheme"], sc["params"], words0)
+    n = 50
+    sim.step(n)
+    _, vq, _, _ = orc.decode(sc["scheme"], sim.words())
+    dv = 40.0 / 2 ** 16
+    expect = -9.8 * 1e-4 * n
+    # per-particle dither noise is bounded by one LSB per step and averages out
+    assert abs(vq[1].mean() - expect) < 4 * 0.5 * dv
+    # the nearest-rounding scheme is biased by 24.6% (closed form above)
+    assert abs(-2 * n * dv - expect) / abs(expect) > 0.2
+
+
+def test_sort_order_properties(orc):
+    rng = np.random.default_rng(9)
+    for dim, res, B in ((2, 64, 16), (3, 32, 8)):
+        n = 3000
+        x = rng.uniform(0.05, 0.95, (dim, n)) ** 2
+        p = WL.params(dim, res, 1e-4, 1e-6)
+        order = orc.sort_order(p, x)
+        assert np.array_equal(np.sort(order), np.arange(n))
+        base = np.clip(np.floor(x * res - 0.5), 0, res - 3).astype(np.int64)
+        nb = -(-res // B)
+        blk = np.zeros(n, dtype=np.int64)
+        cib = np.zeros(n, dtype=np.int64)
+        cell = np.zeros(n, dtype=np.int64)
+        for a in reversed(range(dim)):
+            blk = blk * nb + base[a] // B
+            cib = cib * B + base[a] % B
+            cell = cell * res + base[a]
+        # rank of each particle among earlier slots of its cell
+        rank = np.zeros(n, dtype=np.int64)
+        seen = {}
+        for q in range(n):
+            rank[q] = seen.get(cell[q], 0)
+            seen[cell[q]] = rank[q] + 1
+        key = np.stack([blk[order], rank[order], cib[order], order])
+        for i in range(n - 1):
+            assert tuple(key[:, i]) < tuple(key[:, i + 1])
