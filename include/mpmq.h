@@ -1,0 +1,202 @@
+/*
+ * mpmq.h -- C ABI of the quantized MLS-MPM substep on AMD MI355X (gfx950).
+ *
+ * The library advances an MLS-MPM simulation whose particle state is stored
+ * bit-packed under a quantization scheme, following Liu et al., "Automatic
+ * Quantization for Physics-Based Simulation" (SIGGRAPH 2022):
+ *   - the quantized step model of Eq. 1: each substep evaluates the
+ *     full-precision update on the decoded quantized state and imposes the
+ *     quantization error only when the new state is stored;
+ *   - fixed-point types of Eq. 3 (u = round(v/Delta), Delta = 2^-b R) with
+ *     an affine range [lo, hi), and a shared-exponent float type;
+ *   - non-subtractive dithered rounding of Eq. 11 (Sec. 5), drawn from
+ *     Philox4x32-10 keyed by (seed) and counted by (slot, step, group, tag);
+ *   - the "bit pack" container of Sec. 7 (Figs. 7-8): the components of all
+ *     fields are concatenated in placement order and may span two 32-bit
+ *     words.  Storage is word-major: word k of particle slot p is
+ *     packed[k * capacity_padded + p].
+ *
+ * The scheme is the per-quantity (bits, range) pair that Algorithm 1
+ * outputs, plus the dither flag and the placement order of
+ * bit_pack().place(...) (Sec. 7).  The state is (x, v, C, F) per particle
+ * (the MPM example of Sec. 3.1 / Fig. 3).
+ *
+ * Conventions.  All pointers named "device" are HIP device pointers on the
+ * device that is current when mpmq_create is called; the library never
+ * allocates or frees device memory -- the caller supplies every buffer,
+ * sized by mpmq_query_sizes.  Host structs passed in are copied; nothing is
+ * retained after the call returns.  Work is enqueued on the caller's HIP
+ * stream and is asynchronous unless a function says it synchronizes.  A
+ * context is not thread-safe; separate contexts on separate streams are
+ * independent.  No C++ exception crosses this boundary; errors are returned
+ * as mpmq_status and described by mpmq_last_error(ctx).
+ */
+#ifndef MPMQ_H
+#define MPMQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPMQ_OK = 0,
+    MPMQ_EINVAL = -1,   /* invalid argument, scheme or parameters */
+    MPMQ_ENOMEM = -2,   /* a caller buffer is too small / capacity exceeded */
+    MPMQ_EDEVICE = -3,  /* a HIP call failed; mpmq_last_error has its message */
+    MPMQ_ESTATE = -4,   /* call order (e.g. step before encode) */
+    MPMQ_ENOTIMPL = -5
+} mpmq_status;
+
+/* Particle attributes (Sec. 3.1, Fig. 3). */
+typedef enum { MPMQ_FIELD_X = 0, MPMQ_FIELD_V = 1, MPMQ_FIELD_C = 2, MPMQ_FIELD_F = 3 } mpmq_field;
+
+/* Storage kinds.
+ * MPMQ_FIXED      Eq. 3 over [lo, hi): Delta = (hi-lo) 2^-bits,
+ *                 u = floor((v-lo)*(2^bits/(hi-lo)) + 1/2)  (binary64, ties
+ *                 up; + xi in [0,1) instead of 1/2 when dithered, Eq. 11),
+ *                 clamped to [0, 2^bits-1]; decode fma(u, Delta, lo).
+ *                 1 <= bits <= 32.
+ * MPMQ_SHARED_EXP a vector field sharing one exponent of exp_bits bits:
+ *                 E_max = ceil(log2 hi), E_min = E_max - 2^exp_bits + 1,
+ *                 E = clamp(ilogb(max|v_k|)+1, E_min, E_max), raised by one
+ *                 if a magnitude rounds up to 2^(bits-1);
+ *                 q_k = round(|v_k| 2^(bits-1-E)) in bits-1 magnitude bits +
+ *                 1 sign bit.  2 <= bits <= 32, 1 <= exp_bits <= 8, lo ignored.
+ * MPMQ_RAW_F32    the IEEE float32 bit pattern (bits must be 32): an all-raw
+ *                 scheme is the plain FP32 structure-of-arrays layout. */
+typedef enum { MPMQ_FIXED = 0, MPMQ_SHARED_EXP = 1, MPMQ_RAW_F32 = 2 } mpmq_kind;
+
+/* flags of mpmq_field_scheme */
+#define MPMQ_REL_IDENTITY 1 /* F only: store F - I (diagonal in [lo+1, hi+1)) */
+
+typedef struct {
+    int32_t field;    /* mpmq_field */
+    int32_t kind;     /* mpmq_kind */
+    int32_t bits;     /* bits per component (SHARED_EXP: sign + magnitude) */
+    int32_t exp_bits; /* SHARED_EXP only */
+    int32_t dither;   /* 1: dithered rounding (Eq. 11), 0: round to nearest */
+    int32_t flags;    /* MPMQ_REL_IDENTITY */
+    double lo, hi;
+} mpmq_field_scheme;
+
+typedef struct {
+    int32_t dim;                      /* 2 or 3 */
+    int32_t n_fields;                 /* 4: X, V, C, F each exactly once */
+    const mpmq_field_scheme *fields;  /* array order = bit placement order */
+    uint64_t seed;                    /* Philox key (low word, high word) */
+} mpmq_scheme;
+
+/* MLS-MPM parameters.  Domain [0,1)^dim, grid_res nodes per axis
+ * (dx = 1/grid_res, 8 <= grid_res <= 1024), quadratic B-splines,
+ * fixed-corotated elasticity with Young's modulus E and Poisson ratio nu,
+ * particle mass rho*p_vol.  Within bound_cells nodes of a wall the grid
+ * velocity component pointing into the wall is zeroed.  Particles are
+ * re-sorted by cell at every step s with s % sort_every == 0
+ * (sort_every == 0: only after an encode). */
+typedef struct {
+    int32_t dim, grid_res, bound_cells, sort_every;
+    double dt, gravity[3], E, nu, rho, p_vol;
+} mpmq_params;
+
+typedef struct {
+    int32_t words_per_particle;  /* W = ceil(record_bits / 32) */
+    int32_t record_bits;
+    int64_t capacity_padded;     /* capacity rounded up to a multiple of 256 */
+    int64_t packed_bytes;        /* 4 * W * capacity_padded */
+    int64_t grid_bytes;          /* bytes of EACH of the two grid buffers */
+    int64_t scratch_bytes;       /* sort, work list, flags, counters */
+    int64_t ids_bytes;           /* optional particle-id buffer */
+} mpmq_sizes;
+
+/* Caller-owned device buffers (256-byte aligned).  ids may be NULL: when
+ * given, the library keeps ids[slot] = index of that particle in the last
+ * mpmq_encode input, permuted along with every sort. */
+typedef struct {
+    void *packed;
+    void *grid_a;
+    void *grid_b;
+    void *scratch;
+    void *ids;
+} mpmq_buffers;
+
+typedef struct {
+    int64_t sat[4];    /* codes clamped to the representable range, per field */
+    int64_t nan[4];    /* NaN inputs to the encoder, per field */
+    int64_t up[4];     /* roundings to the upper lattice point, per field */
+    int64_t down[4];   /* roundings to the lower lattice point, per field */
+    int64_t steps;     /* substeps taken by this context */
+    int64_t sorts;     /* particle sorts performed */
+    int64_t fallback;  /* particle-stencils that left their tile (global atomics) */
+    int64_t active_nodes; /* sum over substeps of grid nodes with mass > 0 */
+} mpmq_stats_t;
+
+typedef struct mpmq_ctx mpmq_ctx;
+
+/* Sizes of every buffer for `capacity` particles.  Host only.
+ * EINVAL: invalid scheme or params (mpmq_last_error(NULL) names why). */
+mpmq_status mpmq_query_sizes(const mpmq_scheme *scheme, const mpmq_params *params,
+                             int64_t capacity, mpmq_sizes *out);
+
+/* Creates a context over caller buffers; `hip_stream` is a hipStream_t
+ * (NULL = default stream).  Clears the grid buffers and scratch on the
+ * stream.  EINVAL / ENOMEM (capacity < 1 or > 2^31-256) / EDEVICE. */
+mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params,
+                        const mpmq_buffers *buffers, int64_t capacity, void *hip_stream,
+                        mpmq_ctx **out);
+mpmq_status mpmq_destroy(mpmq_ctx *ctx);
+
+/* Encodes n particles (0 <= n <= capacity) from float32 device arrays in
+ * component-major structure-of-arrays layout: x[c*n+p] (c < dim),
+ * v[c*n+p], C[(i*dim+j)*n+p], F[(i*dim+j)*n+p] (full F, row-major).
+ * Dithered fields use Philox counter (p, step_count, group, 2).  Marks the
+ * state unsorted (the next step sorts) and resets ids to 0..n-1. */
+mpmq_status mpmq_encode(mpmq_ctx *ctx, const float *x, const float *v, const float *C,
+                        const float *F, int64_t n);
+
+/* Decodes the current state into float32 device arrays (same layout, n =
+ * current particle count; the decode is exact in binary64 and rounded once
+ * to float32).  Any pointer may be NULL to skip that field. */
+mpmq_status mpmq_decode(mpmq_ctx *ctx, float *x, float *v, float *C, float *F);
+
+/* Borrowed view of the packed words (device pointer, valid until destroy). */
+mpmq_status mpmq_packed(mpmq_ctx *ctx, const uint32_t **words, int32_t *W, int64_t *n,
+                        int64_t *stride);
+
+/* Advances n_substeps MLS-MPM substeps (Eq. 1 model): sort when due,
+ * P2G, grid update, then one fused kernel per substep that gathers (G2P),
+ * updates x, v, C, F, re-encodes with dithered rounding, stores the words in
+ * place and scatters (P2G) the stored state for the next substep.
+ * Asynchronous.  ESTATE before the first encode. */
+mpmq_status mpmq_step(mpmq_ctx *ctx, int32_t n_substeps);
+
+/* Substep counter (the Philox "step" of the next substep). */
+mpmq_status mpmq_step_count(mpmq_ctx *ctx, int64_t *out);
+
+/* Accumulated statistics.  Synchronizes the stream. */
+mpmq_status mpmq_stats(mpmq_ctx *ctx, mpmq_stats_t *out);
+mpmq_status mpmq_reset_stats(mpmq_ctx *ctx);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * every launch while enabled.  mpmq_kernel_times synchronizes and returns,
+ * for up to `max` kernel names, the launch count and total milliseconds. */
+typedef struct { char name[32]; int64_t launches; double total_ms; } mpmq_kernel_time;
+mpmq_status mpmq_set_timing(mpmq_ctx *ctx, int32_t enable);
+mpmq_status mpmq_kernel_times(mpmq_ctx *ctx, mpmq_kernel_time *out, int32_t max, int32_t *count);
+
+/* Adjoint of the quantized substep (per-field error sensitivities, Eqs.
+ * 8, 12-13).  Not provided by this build: returns MPMQ_ENOTIMPL. */
+typedef struct { int32_t objective; int32_t axis; int32_t steps; int32_t checkpoint_every; } mpmq_adjoint_spec;
+mpmq_status mpmq_adjoint(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, double *G_per_field,
+                         double *g_per_field);
+
+const char *mpmq_error_string(mpmq_status status);
+/* Last error message of ctx (or of the calling thread's last failed
+ * query/create when ctx is NULL).  Never NULL. */
+const char *mpmq_last_error(mpmq_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPMQ_H */

@@ -119,16 +119,20 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* 16-bit dither draw for record component k of particle `slot`. */
-static double dither_xi(uint64_t seed, uint32_t slot, uint32_t step, uint32_t tag, int k)
+/* 16-bit dither draws of one record: draws[k] for record component k. */
+static void dither_draws(uint64_t seed, uint32_t slot, uint32_t step, uint32_t tag, int ncomp, double *draws)
 {
-    uint32_t ctr[4] = {slot, step, (uint32_t)(k / 8), tag};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    uint32_t out[4];
-    orc_philox4x32_10(ctr, key, out);
-    uint32_t word = out[(k % 8) / 2];
-    uint32_t r = (k % 2) ? (word >> 16) : (word & 0xFFFFu);
-    return ((double)r + 0.5) / 65536.0;
+    for (int j = 0; j * 8 < ncomp; ++j) {
+        uint32_t ctr[4] = {slot, step, (uint32_t)j, tag};
+        uint32_t out[4];
+        orc_philox4x32_10(ctr, key, out);
+        for (int i = 0; i < 8 && 8 * j + i < ncomp; ++i) {
+            uint32_t word = out[i / 2];
+            uint32_t r = (i % 2) ? (word >> 16) : (word & 0xFFFFu);
+            draws[8 * j + i] = ((double)r + 0.5) / 65536.0;
+        }
+    }
 }
 
 /* ---- field codecs ---- */
@@ -236,20 +240,20 @@ static void sexp_decode(const orc_field *f, int nc, const uint32_t *codes, doubl
 /* ---- bit packing (Sec. 7) ---- */
 static void put_bits(uint32_t *rec, int off, int nbits, uint32_t code)
 {
-    for (int b = 0; b < nbits; ++b) {
-        int g = off + b;
-        if ((code >> b) & 1u) rec[g >> 5] |= (1u << (g & 31));
-    }
+    /* record bits [off, off+nbits) <- code, LSB first; may touch two words */
+    uint64_t mask = (nbits == 32) ? 0xFFFFFFFFull : ((1ull << nbits) - 1ull);
+    uint64_t v = ((uint64_t)code & mask) << (off & 31);
+    rec[off >> 5] |= (uint32_t)v;
+    if ((off & 31) + nbits > 32) rec[(off >> 5) + 1] |= (uint32_t)(v >> 32);
 }
 
 static uint32_t get_bits(const uint32_t *rec, int off, int nbits)
 {
-    uint32_t code = 0;
-    for (int b = 0; b < nbits; ++b) {
-        int g = off + b;
-        if ((rec[g >> 5] >> (g & 31)) & 1u) code |= (1u << b);
-    }
-    return code;
+    uint64_t lo = rec[off >> 5];
+    uint64_t hi = ((off & 31) + nbits > 32) ? rec[(off >> 5) + 1] : 0u;
+    uint64_t both = lo | (hi << 32);
+    uint64_t mask = (nbits == 32) ? 0xFFFFFFFFull : ((1ull << nbits) - 1ull);
+    return (uint32_t)((both >> (off & 31)) & mask);
 }
 
 /* Encode one particle.  vals[field][comp] are the attribute values (F is the
@@ -261,6 +265,8 @@ static void encode_record(const orc_scheme *s, const double vals[4][9], uint32_t
     memset(rec, 0, sizeof(uint32_t) * (size_t)W);
     int off = 0;
     int k = 0; /* magnitude component index, placement order */
+    double draws[32];
+    dither_draws(s->seed, slot, step, tag, 2 * dim + 2 * dim * dim, draws);
     for (int i = 0; i < 4; ++i) {
         const orc_field *f = &s->f[i];
         int nc = ncomp_of(f->field, dim);
@@ -273,7 +279,7 @@ static void encode_record(const orc_scheme *s, const double vals[4][9], uint32_t
         }
         if (f->kind == ORC_SHARED_EXP) {
             double xi[9];
-            for (int c = 0; c < nc; ++c) xi[c] = dither_xi(s->seed, slot, step, tag, k + c);
+            for (int c = 0; c < nc; ++c) xi[c] = draws[k + c];
             uint32_t codes[10];
             sexp_encode(f, nc, rel, f->dither ? xi : 0, codes, st);
             put_bits(rec, off, f->exp_bits, codes[0]);
@@ -285,7 +291,7 @@ static void encode_record(const orc_scheme *s, const double vals[4][9], uint32_t
                 if (f->kind == ORC_RAW_F32) {
                     code = f32_bits((float)rel[c]);
                 } else {
-                    double xi = f->dither ? dither_xi(s->seed, slot, step, tag, k + c) : -1.0;
+                    double xi = f->dither ? draws[k + c] : -1.0;
                     code = fixed_encode(f, rel[c], xi, st);
                 }
                 put_bits(rec, off, f->bits, code);

@@ -1,0 +1,307 @@
+"""Quantized MLS-MPM substep on AMD MI355X -- Python binding of libmpmq.so.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of ``libmpmq.so`` behind the C ABI of ``include/mpmq.h``.  PyTorch
+provides device memory and the HIP stream.  There is no CPU fallback: if the
+library or a GPU is missing, loading fails with an error.
+
+Schemes and parameters are plain dictionaries (see ``workloads``):
+  scheme = {"dim": 3, "seed": 0, "fields": [
+      {"field": "x", "kind": "fixed", "bits": 21, "lo": 0.0, "hi": 1.0,
+       "dither": True, "rel_identity": False, "exp_bits": 0}, ...]}
+  params = {"dim": 3, "grid_res": 512, "bound_cells": 3, "sort_every": 0,
+            "dt": 1e-4, "gravity": [0, -9.8, 0], "E": 1e3, "nu": 0.2,
+            "rho": 1.0, "p_vol": ...}
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpmq.so")
+
+FIELDS = {"x": 0, "v": 1, "C": 2, "F": 3}
+KINDS = {"fixed": 0, "shared_exp": 1, "raw_f32": 2}
+REL_IDENTITY = 1
+
+STATUS = {0: "MPMQ_OK", -1: "MPMQ_EINVAL", -2: "MPMQ_ENOMEM", -3: "MPMQ_EDEVICE",
+          -4: "MPMQ_ESTATE", -5: "MPMQ_ENOTIMPL"}
+
+
+class MpmqError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class mpmq_field_scheme(ct.Structure):
+    _fields_ = [("field", ct.c_int32), ("kind", ct.c_int32), ("bits", ct.c_int32),
+                ("exp_bits", ct.c_int32), ("dither", ct.c_int32), ("flags", ct.c_int32),
+                ("lo", ct.c_double), ("hi", ct.c_double)]
+
+
+class mpmq_scheme(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("n_fields", ct.c_int32),
+                ("fields", ct.POINTER(mpmq_field_scheme)), ("seed", ct.c_uint64)]
+
+
+class mpmq_params(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("grid_res", ct.c_int32), ("bound_cells", ct.c_int32),
+                ("sort_every", ct.c_int32), ("dt", ct.c_double), ("gravity", ct.c_double * 3),
+                ("E", ct.c_double), ("nu", ct.c_double), ("rho", ct.c_double), ("p_vol", ct.c_double)]
+
+
+class mpmq_sizes(ct.Structure):
+    _fields_ = [("words_per_particle", ct.c_int32), ("record_bits", ct.c_int32),
+                ("capacity_padded", ct.c_int64), ("packed_bytes", ct.c_int64),
+                ("grid_bytes", ct.c_int64), ("scratch_bytes", ct.c_int64), ("ids_bytes", ct.c_int64)]
+
+
+class mpmq_buffers(ct.Structure):
+    _fields_ = [("packed", ct.c_void_p), ("grid_a", ct.c_void_p), ("grid_b", ct.c_void_p),
+                ("scratch", ct.c_void_p), ("ids", ct.c_void_p)]
+
+
+class mpmq_stats_t(ct.Structure):
+    _fields_ = [("sat", ct.c_int64 * 4), ("nan", ct.c_int64 * 4), ("up", ct.c_int64 * 4),
+                ("down", ct.c_int64 * 4), ("steps", ct.c_int64), ("sorts", ct.c_int64),
+                ("fallback", ct.c_int64), ("active_nodes", ct.c_int64)]
+
+
+class mpmq_kernel_time(ct.Structure):
+    _fields_ = [("name", ct.c_char * 32), ("launches", ct.c_int64), ("total_ms", ct.c_double)]
+
+
+class mpmq_adjoint_spec(ct.Structure):
+    _fields_ = [("objective", ct.c_int32), ("axis", ct.c_int32), ("steps", ct.c_int32),
+                ("checkpoint_every", ct.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libmpmq.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2207_04658_amd/build.py "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ct.CDLL(path)
+    P = ct.c_void_p
+    S = ct.c_int
+    sig = {
+        "mpmq_query_sizes": [ct.POINTER(mpmq_scheme), ct.POINTER(mpmq_params), ct.c_int64, ct.POINTER(mpmq_sizes)],
+        "mpmq_create": [ct.POINTER(mpmq_scheme), ct.POINTER(mpmq_params), ct.POINTER(mpmq_buffers), ct.c_int64, P,
+                        ct.POINTER(P)],
+        "mpmq_destroy": [P],
+        "mpmq_encode": [P, P, P, P, P, ct.c_int64],
+        "mpmq_decode": [P, P, P, P, P],
+        "mpmq_packed": [P, ct.POINTER(P), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)],
+        "mpmq_step": [P, ct.c_int32],
+        "mpmq_step_count": [P, ct.POINTER(ct.c_int64)],
+        "mpmq_stats": [P, ct.POINTER(mpmq_stats_t)],
+        "mpmq_reset_stats": [P],
+        "mpmq_set_timing": [P, ct.c_int32],
+        "mpmq_kernel_times": [P, ct.POINTER(mpmq_kernel_time), ct.c_int32, ct.POINTER(ct.c_int32)],
+        "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = S
+    L.mpmq_error_string.argtypes = [S]
+    L.mpmq_error_string.restype = ct.c_char_p
+    L.mpmq_last_error.argtypes = [P]
+    L.mpmq_last_error.restype = ct.c_char_p
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
+            "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats",
+            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint", "mpmq_error_string",
+            "mpmq_last_error"]
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = load().mpmq_last_error(ctx).decode()
+        raise MpmqError(status, msg)
+
+
+def make_scheme(scheme: dict):
+    """Returns (mpmq_scheme, keep-alive field array)."""
+    fields = (mpmq_field_scheme * len(scheme["fields"]))()
+    for i, f in enumerate(scheme["fields"]):
+        fields[i].field = FIELDS[f["field"]]
+        fields[i].kind = KINDS[f["kind"]]
+        fields[i].bits = int(f.get("bits", 32))
+        fields[i].exp_bits = int(f.get("exp_bits", 0))
+        fields[i].dither = int(bool(f.get("dither", False)))
+        fields[i].flags = REL_IDENTITY if f.get("rel_identity", False) else 0
+        fields[i].lo = float(f.get("lo", 0.0))
+        fields[i].hi = float(f.get("hi", 1.0))
+    s = mpmq_scheme()
+    s.dim = scheme["dim"]
+    s.n_fields = len(scheme["fields"])
+    s.fields = ct.cast(fields, ct.POINTER(mpmq_field_scheme))
+    s.seed = int(scheme.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
+    return s, fields
+
+
+def make_params(params: dict):
+    p = mpmq_params()
+    p.dim = params["dim"]
+    p.grid_res = params["grid_res"]
+    p.bound_cells = params.get("bound_cells", 3)
+    p.sort_every = params.get("sort_every", 0)
+    p.dt = params["dt"]
+    g = list(params.get("gravity", [0.0, -9.8, 0.0])) + [0.0, 0.0, 0.0]
+    for a in range(3):
+        p.gravity[a] = g[a]
+    p.E = params["E"]
+    p.nu = params["nu"]
+    p.rho = params["rho"]
+    p.p_vol = params["p_vol"]
+    return p
+
+
+def mpmq_query_sizes(scheme: dict, params: dict, capacity: int) -> dict:
+    s, keep = make_scheme(scheme)
+    p = make_params(params)
+    out = mpmq_sizes()
+    _check(load().mpmq_query_sizes(ct.byref(s), ct.byref(p), int(capacity), ct.byref(out)))
+    return {k: getattr(out, k) for k, _ in mpmq_sizes._fields_}
+
+
+class Context:
+    """One simulation: owns torch device buffers and an mpmq_ctx.
+
+    Methods map one-to-one on the C ABI: encode, decode, step, packed,
+    stats, kernel_times.  All device work is enqueued on `stream` (default:
+    torch's current stream)."""
+
+    def __init__(self, scheme: dict, params: dict, capacity: int, stream=None, track_ids=True,
+                 device=None):
+        import torch
+        L = load()
+        self.scheme, self.params = scheme, params
+        self.dim = scheme["dim"]
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.sizes = mpmq_query_sizes(scheme, params, capacity)
+        sz = self.sizes
+        u8 = torch.uint8
+
+        def buf(nbytes):
+            return torch.empty(max(int(nbytes), 256), dtype=u8, device=self.device)
+
+        self.packed = buf(sz["packed_bytes"])
+        self.grid_a = buf(sz["grid_bytes"])
+        self.grid_b = buf(sz["grid_bytes"])
+        self.scratch = buf(sz["scratch_bytes"])
+        self.ids_buf = buf(sz["ids_bytes"]) if track_ids else None
+        bufs = mpmq_buffers(self.packed.data_ptr(), self.grid_a.data_ptr(), self.grid_b.data_ptr(),
+                            self.scratch.data_ptr(), self.ids_buf.data_ptr() if track_ids else None)
+        s, keep = make_scheme(scheme)
+        p = make_params(params)
+        h = ct.c_void_p()
+        _check(L.mpmq_create(ct.byref(s), ct.byref(p), ct.byref(bufs), int(capacity),
+                             ct.c_void_p(self.stream.cuda_stream), ct.byref(h)))
+        self._h = h
+        self.capacity = capacity
+        self.n = 0
+
+    # -- C ABI calls ----------------------------------------------------------
+    def encode(self, x, v, C, F):
+        """x, v: [dim, n]; C, F: [dim*dim, n] float32 CUDA tensors (contiguous)."""
+        import torch
+        ts = [t.to(device=self.device, dtype=torch.float32).contiguous() for t in (x, v, C, F)]
+        n = ts[0].shape[-1]
+        _check(load().mpmq_encode(self._h, *[t.data_ptr() for t in ts], int(n)), self._h)
+        self._keep = ts  # inputs stay alive until the stream has consumed them
+        self.n = n
+
+    def decode(self):
+        import torch
+        d, n = self.dim, self.n
+        out = [torch.empty((k, n), dtype=torch.float32, device=self.device) for k in (d, d, d * d, d * d)]
+        _check(load().mpmq_decode(self._h, *[t.data_ptr() for t in out]), self._h)
+        return tuple(out)
+
+    def step(self, n_substeps=1):
+        _check(load().mpmq_step(self._h, int(n_substeps)), self._h)
+
+    def step_count(self):
+        v = ct.c_int64()
+        _check(load().mpmq_step_count(self._h, ct.byref(v)), self._h)
+        return v.value
+
+    def packed_view(self):
+        """Packed words as a [W, n] int32 view (strided by the padded capacity)."""
+        import torch
+        W = self.sizes["words_per_particle"]
+        cap = self.sizes["capacity_padded"]
+        return self.packed[: 4 * W * cap].view(torch.int32).view(W, cap)[:, : self.n]
+
+    def words(self):
+        """Packed words copied to host as a [W, n] uint32 numpy array."""
+        import numpy as np
+        self.stream.synchronize()
+        return self.packed_view().cpu().numpy().view(np.uint32)
+
+    def ids(self):
+        import numpy as np
+        import torch
+        if self.ids_buf is None:
+            raise ValueError("context created without id tracking")
+        self.stream.synchronize()
+        return self.ids_buf[: 4 * self.n].view(torch.int32).cpu().numpy().astype(np.int64)
+
+    def stats(self):
+        st = mpmq_stats_t()
+        _check(load().mpmq_stats(self._h, ct.byref(st)), self._h)
+        names = ["x", "v", "C", "F"]
+        out = {names[i]: {"sat": st.sat[i], "nan": st.nan[i], "up": st.up[i], "down": st.down[i]}
+               for i in range(4)}
+        out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes)
+        return out
+
+    def reset_stats(self):
+        _check(load().mpmq_reset_stats(self._h), self._h)
+
+    def set_timing(self, enable=True):
+        _check(load().mpmq_set_timing(self._h, 1 if enable else 0), self._h)
+
+    def kernel_times(self, clear=False):
+        arr = (mpmq_kernel_time * 32)()
+        cnt = ct.c_int32()
+        _check(load().mpmq_kernel_times(self._h, arr, -1 if clear else 32, ct.byref(cnt)), self._h)
+        if clear:
+            return {}
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(cnt.value, 32))}
+
+    def adjoint(self, spec=None):
+        import numpy as np
+        G = np.zeros(4)
+        g = np.zeros(4)
+        s = mpmq_adjoint_spec(0, 0, 0, 8) if spec is None else spec
+        st = load().mpmq_adjoint(self._h, ct.byref(s), G.ctypes.data_as(ct.c_void_p), g.ctypes.data_as(ct.c_void_p))
+        _check(st, self._h)
+        return G, g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.stream.synchronize()
+            load().mpmq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,114 @@
+// mpmq_internal.hpp -- descriptors shared by the host runtime and the gfx950
+// kernels of the quantized MLS-MPM library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpmq {
+
+// Sort / tile geometry.  Particles are sorted by cell and grouped by blocks of
+// BLK^dim cells; each work item covers one block's particles (or a chunk of
+// them) and stages a (BLK+4)^dim node tile in LDS (one node of margin on
+// each side beyond the 3-node stencil reach, so particles that drifted by up
+// to one cell since the sort stay inside the tile).
+template <int DIM> struct Geo;
+template <> struct Geo<3> {
+    static constexpr int BLK = 8, LOG = 3, CPB = 512, TB = 12, TN = 1728, NST = 27;
+};
+template <> struct Geo<2> {
+    static constexpr int BLK = 16, LOG = 4, CPB = 256, TB = 20, TN = 400, NST = 9;
+};
+
+constexpr int WG = 256;          // threads per work-group of the particle kernels
+constexpr int MAX_WORDS = 32;    // record <= 1024 bits
+
+// One field's codec constants (indexed by field id x=0, v=1, C=2, F=3).
+struct DevField {
+    int32_t kind, bits, exp_bits, dither;
+    int32_t rel, ncomp, k0, pad0;        // k0: first Philox component index
+    int32_t emin, emax;                  // SHARED_EXP exponent range
+    uint32_t exp_desc, exp_mask;         // SHARED_EXP exponent location
+    uint32_t mag_mask, pad1;             // SHARED_EXP magnitude mask (bits-1 ones)
+    double lo, delta, inv, maxc;         // FIXED: range start, step, 2^b/(hi-lo), 2^b-1
+};
+
+// Component location word | hiword<<8 | shift<<16 | spans<<24.
+struct DevScheme {
+    int32_t dim, W;
+    uint32_t seed_lo, seed_hi;
+    uint32_t dither_groups;              // bit j: Philox group j is needed
+    int32_t pad[3];
+    DevField f[4];
+    uint32_t cdesc[4][9];
+    uint32_t cmask[4][9];
+};
+
+struct DevParams {
+    int32_t dim, res, bound, nb;         // nb: node blocks per axis
+    float dt, inv_dx, dx, mu, la, p_mass, stress_coef, pad;
+    float g[3], pad2;
+    double dt_d, inv_dx_d;
+};
+
+// Statistics slots (uint64) in scratch.
+enum {
+    ST_SAT = 0, ST_NAN = 4, ST_UP = 8, ST_DOWN = 12, ST_FALLBACK = 16, ST_ACTIVE = 17,
+    ST_COUNT = 24
+};
+
+// Device scratch layout (byte offsets, all 256-aligned).
+struct Scratch {
+    int64_t keys, vals, keys2, vals2;    // radix sort (Ncap each)
+    int64_t cells;                       // ncells + 1 counts -> exclusive starts
+    int64_t scan_tmp;                    // scan partial sums (all levels)
+    int64_t hist;                        // radix histogram, 256 * tiles
+    int64_t block_items;                 // nblocks + 1 item counts -> offsets
+    int64_t items;                       // int4 work items
+    int64_t flags;                       // 2 * nblocks uint32 touched flags
+    int64_t stats;                       // ST_COUNT uint64
+    int64_t misc;                        // 64 uint32 (n_items, ...)
+    int64_t total;
+    int64_t ncells, nblocks, max_items, hist_entries, scan_tmp_entries;
+};
+
+struct WorkItem { int32_t block, p0, p1, pad; };
+
+// ---- launchers (kernels.hip) ----
+struct Launch {
+    hipStream_t stream;
+};
+
+hipError_t launch_encode(int dim, int wm, const DevScheme &s, const float *x, const float *v,
+                         const float *C, const float *F, int64_t n, int64_t cap, uint32_t *words,
+                         uint32_t *ids, uint32_t step, uint32_t tag, uint64_t *stats, hipStream_t st);
+hipError_t launch_decode(int dim, int wm, const DevScheme &s, const uint32_t *words, int64_t n,
+                         int64_t cap, float *x, float *v, float *C, float *F, hipStream_t st);
+hipError_t launch_sort_keys(int dim, int wm, const DevScheme &s, const DevParams &p,
+                            const uint32_t *words, int64_t n, int64_t cap, uint32_t *keys,
+                            uint32_t *vals, uint32_t *cell_count, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t st);
+hipError_t launch_scan(uint32_t *data, int64_t n, uint32_t *tmp, hipStream_t st);
+hipError_t launch_radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                             int64_t n, int shift, uint32_t *hist, uint32_t *scan_tmp, hipStream_t st);
+hipError_t launch_layer(int dim, const uint32_t *cell_start, const uint32_t *sorted_vals,
+                        int64_t nblocks, uint32_t *perm, uint32_t *block_items, int item_cap,
+                        hipStream_t st);
+hipError_t launch_items(const uint32_t *cell_start, const uint32_t *block_items_scanned,
+                        int64_t nblocks, int cpb, int item_cap, WorkItem *items, uint32_t *n_items,
+                        hipStream_t st);
+hipError_t launch_gather_u32(const uint32_t *in, const uint32_t *perm, uint32_t *out, int64_t n,
+                             hipStream_t st);
+hipError_t launch_copy_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
+hipError_t launch_p2g(int dim, int wm, const DevScheme &s, const DevParams &p, const uint32_t *words,
+                      int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
+                      float4 *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st);
+hipError_t launch_grid_update(int dim, const DevParams &p, float4 *gcur, float4 *gnxt,
+                              uint32_t *flags_cur, uint32_t *flags_nxt, int64_t nblocks,
+                              uint64_t *stats, hipStream_t st);
+hipError_t launch_clear_touched(int dim, float4 *g, uint32_t *flags, int64_t nblocks, hipStream_t st);
+hipError_t launch_substep(int dim, int wm, const DevScheme &s, const DevParams &p, uint32_t *words,
+                          int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
+                          const float4 *gcur, float4 *gnxt, uint32_t *flags_nxt, uint32_t step,
+                          int do_p2g, int collect_stats, uint64_t *stats, hipStream_t st);
+
+}  // namespace mpmq

@@ -1,0 +1,530 @@
+// runtime.hip -- host side of the C ABI declared in include/mpmq.h: scheme
+// compilation (bit offsets, codec constants), carving of the caller's
+// buffers, and the launch sequence of one substep on the caller's stream.
+#include "../../include/mpmq.h"
+#include "mpmq_internal.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace mpmq;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+struct EventPair {
+    const char *name;
+    hipEvent_t a, b;
+};
+
+int ceil_log2_double(double hi) {
+    int ex;
+    const double m = std::frexp(hi, &ex);
+    return (m == 0.5) ? ex - 1 : ex;
+}
+
+int ncomp(int field, int dim) { return (field == MPMQ_FIELD_X || field == MPMQ_FIELD_V) ? dim : dim * dim; }
+
+bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::string &err) {
+    if (!sc || !sc->fields) { err = "scheme or scheme->fields is NULL"; return false; }
+    if (sc->dim != 2 && sc->dim != 3) { err = "scheme dim must be 2 or 3"; return false; }
+    if (sc->n_fields != 4) { err = "scheme must list the 4 fields x, v, C, F"; return false; }
+    std::memset(&ds, 0, sizeof(ds));
+    ds.dim = sc->dim;
+    ds.seed_lo = (uint32_t)sc->seed;
+    ds.seed_hi = (uint32_t)(sc->seed >> 32);
+    bool seen[4] = {false, false, false, false};
+    int off = 0, k = 0;
+    static const char *names[4] = {"x", "v", "C", "F"};
+    for (int i = 0; i < 4; ++i) {
+        const mpmq_field_scheme &f = sc->fields[i];
+        if (f.field < 0 || f.field > 3 || seen[f.field]) { err = "fields must be x, v, C, F each exactly once"; return false; }
+        seen[f.field] = true;
+        const char *nm = names[f.field];
+        const int nc = ncomp(f.field, sc->dim);
+        const bool rel = (f.flags & MPMQ_REL_IDENTITY) != 0;
+        if (rel && f.field != MPMQ_FIELD_F) { err = std::string("REL_IDENTITY is only valid for F (field ") + nm + ")"; return false; }
+        DevField &d = ds.f[f.field];
+        d.kind = f.kind;
+        d.bits = f.bits;
+        d.exp_bits = f.exp_bits;
+        d.dither = f.dither ? 1 : 0;
+        d.rel = rel ? 1 : 0;
+        d.ncomp = nc;
+        d.k0 = k;
+        if (f.kind == MPMQ_FIXED) {
+            if (f.bits < 1 || f.bits > 32) { err = std::string("field ") + nm + ": FIXED bits must be in [1, 32]"; return false; }
+            if (!(f.hi > f.lo) || !std::isfinite(f.lo) || !std::isfinite(f.hi)) { err = std::string("field ") + nm + ": need finite lo < hi"; return false; }
+            d.lo = f.lo;
+            d.delta = std::ldexp(f.hi - f.lo, -f.bits);
+            d.inv = std::ldexp(1.0, f.bits) / (f.hi - f.lo);
+            d.maxc = std::ldexp(1.0, f.bits) - 1.0;
+        } else if (f.kind == MPMQ_SHARED_EXP) {
+            if (f.bits < 2 || f.bits > 32) { err = std::string("field ") + nm + ": SHARED_EXP bits must be in [2, 32]"; return false; }
+            if (f.exp_bits < 1 || f.exp_bits > 8) { err = std::string("field ") + nm + ": exp_bits must be in [1, 8]"; return false; }
+            if (!(f.hi > 0.0) || !std::isfinite(f.hi) || rel) { err = std::string("field ") + nm + ": SHARED_EXP needs finite hi > 0 and no REL_IDENTITY"; return false; }
+            d.emax = ceil_log2_double(f.hi);
+            d.emin = d.emax - ((1 << f.exp_bits) - 1);
+            d.mag_mask = (uint32_t)((1ull << (f.bits - 1)) - 1ull);
+            const int sh = off & 31;
+            const int span = (sh + f.exp_bits > 32) ? 1 : 0;
+            d.exp_desc = (uint32_t)(off >> 5) | ((uint32_t)((off >> 5) + span) << 8) | ((uint32_t)sh << 16) |
+                         ((uint32_t)span << 24);
+            d.exp_mask = (uint32_t)((1ull << f.exp_bits) - 1ull);
+            off += f.exp_bits;
+        } else if (f.kind == MPMQ_RAW_F32) {
+            if (f.bits != 32) { err = std::string("field ") + nm + ": RAW_F32 bits must be 32"; return false; }
+        } else {
+            err = std::string("field ") + nm + ": unknown kind";
+            return false;
+        }
+        for (int c = 0; c < nc; ++c) {
+            const int sh = off & 31;
+            const int span = (sh + f.bits > 32) ? 1 : 0;
+            ds.cdesc[f.field][c] = (uint32_t)(off >> 5) | ((uint32_t)((off >> 5) + span) << 8) |
+                                   ((uint32_t)sh << 16) | ((uint32_t)span << 24);
+            ds.cmask[f.field][c] = (f.bits == 32) ? 0xffffffffu : (uint32_t)((1ull << f.bits) - 1ull);
+            off += f.bits;
+        }
+        if (d.dither && f.kind != MPMQ_RAW_F32)
+            for (int c = 0; c < nc; ++c) ds.dither_groups |= 1u << ((k + c) / 8);
+        k += nc;
+    }
+    if (off > 32 * MAX_WORDS) { err = "record longer than 1024 bits"; return false; }
+    total_bits = off;
+    ds.W = (off + 31) / 32;
+    return true;
+}
+
+bool compile_params(const mpmq_params *pp, int dim, DevParams &dp, std::string &err) {
+    if (!pp) { err = "params is NULL"; return false; }
+    if (pp->dim != dim) { err = "params dim differs from scheme dim"; return false; }
+    if (pp->grid_res < 8 || pp->grid_res > 1024) { err = "grid_res must be in [8, 1024]"; return false; }
+    if (pp->bound_cells < 0 || pp->sort_every < 0) { err = "bound_cells and sort_every must be >= 0"; return false; }
+    if (!(pp->dt > 0) || !(pp->E > 0) || !(pp->rho > 0) || !(pp->p_vol > 0) || !(pp->nu > -1.0 && pp->nu < 0.5)) {
+        err = "need dt, E, rho, p_vol > 0 and -1 < nu < 0.5";
+        return false;
+    }
+    std::memset(&dp, 0, sizeof(dp));
+    const int B = dim == 3 ? Geo<3>::BLK : Geo<2>::BLK;
+    dp.dim = dim;
+    dp.res = pp->grid_res;
+    dp.bound = pp->bound_cells;
+    dp.nb = (pp->grid_res + B - 1) / B;
+    const double inv_dx = (double)pp->grid_res;
+    const double mu = pp->E / (2.0 * (1.0 + pp->nu));
+    const double la = pp->E * pp->nu / ((1.0 + pp->nu) * (1.0 - 2.0 * pp->nu));
+    dp.dt = (float)pp->dt;
+    dp.inv_dx = (float)inv_dx;
+    dp.dx = (float)(1.0 / inv_dx);
+    dp.mu = (float)mu;
+    dp.la = (float)la;
+    dp.p_mass = (float)(pp->rho * pp->p_vol);
+    dp.stress_coef = (float)(-pp->dt * pp->p_vol * 4.0 * inv_dx * inv_dx);
+    for (int a = 0; a < 3; ++a) dp.g[a] = (float)pp->gravity[a];
+    dp.dt_d = pp->dt;
+    dp.inv_dx_d = inv_dx;
+    return true;
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+Scratch plan_scratch(int dim, int res, int64_t cap_pad) {
+    Scratch s;
+    std::memset(&s, 0, sizeof(s));
+    const int B = dim == 3 ? Geo<3>::BLK : Geo<2>::BLK;
+    const int CPB = dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
+    const int64_t nb = (res + B - 1) / B;
+    s.nblocks = dim == 3 ? nb * nb * nb : nb * nb;
+    s.ncells = s.nblocks * CPB;
+    const int64_t tiles = (cap_pad + 4095) / 4096;
+    s.hist_entries = 256 * tiles;
+    int64_t big = std::max<int64_t>(s.ncells + 1, std::max<int64_t>(s.hist_entries, s.nblocks + 1));
+    s.scan_tmp_entries = 0;
+    for (int64_t lvl = big; lvl > 4096;) {
+        lvl = (lvl + 4095) / 4096;
+        s.scan_tmp_entries += lvl;
+    }
+    s.scan_tmp_entries += 64;
+    s.max_items = std::min<int64_t>(s.nblocks, cap_pad) + cap_pad / 256 + 2;
+    int64_t o = 0;
+    s.keys = o; o = align256(o + 4 * cap_pad);
+    s.vals = o; o = align256(o + 4 * cap_pad);
+    s.keys2 = o; o = align256(o + 4 * cap_pad);
+    s.vals2 = o; o = align256(o + 4 * cap_pad);
+    s.cells = o; o = align256(o + 4 * (s.ncells + 1));
+    s.scan_tmp = o; o = align256(o + 4 * s.scan_tmp_entries);
+    s.hist = o; o = align256(o + 4 * s.hist_entries);
+    s.block_items = o; o = align256(o + 4 * (s.nblocks + 1));
+    s.items = o; o = align256(o + 16 * s.max_items);
+    s.flags = o; o = align256(o + 4 * 2 * s.nblocks);
+    s.stats = o; o = align256(o + 8 * ST_COUNT);
+    s.misc = o; o = align256(o + 256);
+    s.total = o;
+    return s;
+}
+
+}  // namespace
+
+struct mpmq_ctx {
+    DevScheme ds;
+    DevParams dp;
+    mpmq_params params;
+    int dim = 0, W = 0, wm = 16, record_bits = 0;
+    int64_t cap = 0, cap_pad = 0;
+    hipStream_t stream = nullptr;
+    uint32_t *words = nullptr;
+    float4 *grid[2] = {nullptr, nullptr};
+    uint32_t *ids = nullptr;
+    char *scratch = nullptr;
+    Scratch sp;
+    int64_t n = 0, step = 0, sorted_at = -1, sorts = 0, steps_taken = 0;
+    bool encoded = false, sorted = false, p2g_ready = false;
+    int item_cap = 256, launch_grid = 1;
+    bool timing = false;
+    std::vector<EventPair> events;
+    std::map<std::string, std::pair<int64_t, double>> times;
+    std::string err;
+
+    uint32_t *u32(int64_t off) { return reinterpret_cast<uint32_t *>(scratch + off); }
+    uint64_t *stats() { return reinterpret_cast<uint64_t *>(scratch + sp.stats); }
+    uint32_t *flags(int i) { return u32(sp.flags) + (int64_t)i * sp.nblocks; }
+    uint32_t *n_items() { return u32(sp.misc); }
+    WorkItem *items() { return reinterpret_cast<WorkItem *>(scratch + sp.items); }
+};
+
+namespace {
+
+mpmq_status fail(mpmq_ctx *ctx, mpmq_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    else g_last_error = msg;
+    return st;
+}
+
+#define HIPCHK(ctx, call, what)                                                                        \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(ctx, MPMQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+// Records the events of a timed launch.
+struct Timed {
+    mpmq_ctx *c;
+    EventPair ev;
+    bool on;
+    Timed(mpmq_ctx *ctx, const char *name) : c(ctx), on(ctx->timing) {
+        if (on) {
+            ev.name = name;
+            (void)hipEventCreate(&ev.a);
+            (void)hipEventCreate(&ev.b);
+            (void)hipEventRecord(ev.a, c->stream);
+        }
+    }
+    ~Timed() {
+        if (on) {
+            (void)hipEventRecord(ev.b, c->stream);
+            c->events.push_back(ev);
+        }
+    }
+};
+
+mpmq_status do_sort(mpmq_ctx *c) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->n;
+    const Scratch &s = c->sp;
+    const int cpb = c->dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
+    uint32_t *cells = c->u32(s.cells);
+    // item size: enough items to fill the chip on small scenes, big tiles on large ones
+    int cap = 256;
+    while (cap < 4096 && (int64_t)cap * 2 * 2048 <= n) cap *= 2;
+    c->item_cap = cap;
+    const int64_t upper = std::min<int64_t>(s.nblocks, n) + (n + cap - 1) / cap + 1;
+    c->launch_grid = (int)std::max<int64_t>(1, std::min<int64_t>(upper, 4096));
+    Timed t(c, "sort");
+    HIPCHK(c, launch_fill_u32(cells, 0u, s.ncells + 1, st), "sort: clear cells");
+    HIPCHK(c, launch_sort_keys(c->dim, c->wm, c->ds, c->dp, c->words, n, c->cap_pad, c->u32(s.keys),
+                               c->u32(s.vals), cells, st), "sort: keys");
+    int kbits = 1;
+    while (((int64_t)1 << kbits) < s.ncells) ++kbits;
+    uint32_t *ka = c->u32(s.keys), *va = c->u32(s.vals), *kb = c->u32(s.keys2), *vb = c->u32(s.vals2);
+    for (int shift = 0; shift < kbits; shift += 8) {
+        HIPCHK(c, launch_radix_pass(ka, va, kb, vb, n, shift, c->u32(s.hist), c->u32(s.scan_tmp), st), "sort: radix");
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    // ka/va: keys and original slots in cell order (stable)
+    HIPCHK(c, launch_scan(cells, s.ncells + 1, c->u32(s.scan_tmp), st), "sort: cell scan");
+    uint32_t *perm = ka;  // keys no longer needed
+    uint32_t *tmp = kb;
+    uint32_t *bitems = c->u32(s.block_items);
+    HIPCHK(c, launch_layer(c->dim, cells, va, s.nblocks, perm, bitems, cap, st), "sort: layer");
+    HIPCHK(c, launch_scan(bitems, s.nblocks + 1, c->u32(s.scan_tmp), st), "sort: item scan");
+    HIPCHK(c, launch_items(cells, bitems, s.nblocks, cpb, cap, c->items(), c->n_items(), st), "sort: items");
+    for (int k = 0; k < c->W; ++k) {
+        uint32_t *row = c->words + (int64_t)k * c->cap_pad;
+        HIPCHK(c, launch_gather_u32(row, perm, tmp, n, st), "sort: permute");
+        HIPCHK(c, launch_copy_u32(tmp, row, n, st), "sort: permute");
+    }
+    if (c->ids) {
+        HIPCHK(c, launch_gather_u32(c->ids, perm, tmp, n, st), "sort: ids");
+        HIPCHK(c, launch_copy_u32(tmp, c->ids, n, st), "sort: ids");
+    }
+    c->sorts += 1;
+    return MPMQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpmq_error_string(mpmq_status s) {
+    switch (s) {
+    case MPMQ_OK: return "ok";
+    case MPMQ_EINVAL: return "invalid argument";
+    case MPMQ_ENOMEM: return "buffer too small or capacity exceeded";
+    case MPMQ_EDEVICE: return "HIP error";
+    case MPMQ_ESTATE: return "invalid call order";
+    case MPMQ_ENOTIMPL: return "not implemented";
+    }
+    return "unknown status";
+}
+
+const char *mpmq_last_error(mpmq_ctx *ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+mpmq_status mpmq_query_sizes(const mpmq_scheme *scheme, const mpmq_params *params, int64_t capacity,
+                             mpmq_sizes *out) {
+    if (!out) return fail(nullptr, MPMQ_EINVAL, "out is NULL");
+    DevScheme ds;
+    DevParams dp;
+    int bits = 0;
+    std::string err;
+    if (!compile_scheme(scheme, ds, bits, err)) return fail(nullptr, MPMQ_EINVAL, err);
+    if (!compile_params(params, ds.dim, dp, err)) return fail(nullptr, MPMQ_EINVAL, err);
+    if (capacity < 1 || capacity > (int64_t)0x7fffff00) return fail(nullptr, MPMQ_ENOMEM, "capacity must be in [1, 2^31-256]");
+    const int64_t cap_pad = (capacity + 255) & ~(int64_t)255;
+    const Scratch sp = plan_scratch(ds.dim, dp.res, cap_pad);
+    const int CPB = ds.dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
+    out->words_per_particle = ds.W;
+    out->record_bits = bits;
+    out->capacity_padded = cap_pad;
+    out->packed_bytes = 4 * (int64_t)ds.W * cap_pad;
+    out->grid_bytes = 16 * sp.nblocks * CPB;
+    out->scratch_bytes = sp.total;
+    out->ids_bytes = 4 * cap_pad;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params, const mpmq_buffers *buffers,
+                        int64_t capacity, void *hip_stream, mpmq_ctx **out) {
+    if (!out || !buffers) return fail(nullptr, MPMQ_EINVAL, "out or buffers is NULL");
+    *out = nullptr;
+    mpmq_sizes sz;
+    mpmq_status st = mpmq_query_sizes(scheme, params, capacity, &sz);
+    if (st != MPMQ_OK) return st;
+    if (!buffers->packed || !buffers->grid_a || !buffers->grid_b || !buffers->scratch)
+        return fail(nullptr, MPMQ_EINVAL, "packed, grid_a, grid_b and scratch buffers are required");
+    const uintptr_t al = (uintptr_t)buffers->packed | (uintptr_t)buffers->grid_a | (uintptr_t)buffers->grid_b |
+                         (uintptr_t)buffers->scratch | (uintptr_t)buffers->ids;
+    if (al & 255u) return fail(nullptr, MPMQ_EINVAL, "buffers must be 256-byte aligned");
+    mpmq_ctx *c = new mpmq_ctx();
+    int bits = 0;
+    std::string err;
+    compile_scheme(scheme, c->ds, bits, err);
+    compile_params(params, c->ds.dim, c->dp, err);
+    c->params = *params;
+    c->dim = c->ds.dim;
+    c->W = c->ds.W;
+    c->wm = c->W < 16 ? 16 : 32;
+    c->record_bits = bits;
+    c->cap = capacity;
+    c->cap_pad = sz.capacity_padded;
+    c->stream = (hipStream_t)hip_stream;
+    c->words = (uint32_t *)buffers->packed;
+    c->grid[0] = (float4 *)buffers->grid_a;
+    c->grid[1] = (float4 *)buffers->grid_b;
+    c->scratch = (char *)buffers->scratch;
+    c->ids = (uint32_t *)buffers->ids;
+    c->sp = plan_scratch(c->dim, c->dp.res, c->cap_pad);
+    hipError_t e = hipMemsetAsync(c->grid[0], 0, sz.grid_bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->grid[1], 0, sz.grid_bytes, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.flags, 0, 4 * 2 * c->sp.nblocks, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.stats, 0, 8 * ST_COUNT, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.misc, 0, 256, c->stream);
+    if (e != hipSuccess) {
+        g_last_error = std::string("create: ") + hipGetErrorString(e);
+        delete c;
+        return MPMQ_EDEVICE;
+    }
+    *out = c;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_destroy(mpmq_ctx *ctx) {
+    if (!ctx) return MPMQ_OK;
+    for (auto &ev : ctx->events) {
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+    }
+    delete ctx;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_encode(mpmq_ctx *c, const float *x, const float *v, const float *C, const float *F, int64_t n) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    if (n < 0 || n > c->cap) return fail(c, MPMQ_ENOMEM, "n exceeds capacity");
+    if (n > 0 && (!x || !v || !C || !F)) return fail(c, MPMQ_EINVAL, "x, v, C and F are required");
+    {
+        Timed t(c, "encode");
+        HIPCHK(c, launch_encode(c->dim, c->wm, c->ds, x, v, C, F, n, c->cap_pad, c->words, c->ids,
+                                (uint32_t)c->step, 2u, c->stats(), c->stream), "encode");
+    }
+    c->n = n;
+    c->encoded = true;
+    c->sorted = false;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_decode(mpmq_ctx *c, float *x, float *v, float *C, float *F) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    if (!c->encoded) return fail(c, MPMQ_ESTATE, "decode before encode");
+    Timed t(c, "decode");
+    HIPCHK(c, launch_decode(c->dim, c->wm, c->ds, c->words, c->n, c->cap_pad, x, v, C, F, c->stream), "decode");
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_packed(mpmq_ctx *c, const uint32_t **words, int32_t *W, int64_t *n, int64_t *stride) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    if (words) *words = c->words;
+    if (W) *W = c->W;
+    if (n) *n = c->n;
+    if (stride) *stride = c->cap_pad;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_step(mpmq_ctx *c, int32_t n_substeps) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    if (n_substeps < 0) return fail(c, MPMQ_EINVAL, "n_substeps < 0");
+    if (!c->encoded) return fail(c, MPMQ_ESTATE, "step before encode");
+    if (c->n == 0) {
+        c->step += n_substeps;
+        c->steps_taken += n_substeps;
+        return MPMQ_OK;
+    }
+    hipStream_t st = c->stream;
+    const int S = c->params.sort_every;
+    for (int32_t it = 0; it < n_substeps; ++it) {
+        const int64_t s = c->step;
+        const int cur = (int)(s & 1), nxt = cur ^ 1;
+        const bool need_sort = !c->sorted || (S > 0 && s % S == 0 && c->sorted_at != s);
+        if (need_sort) {
+            if (c->p2g_ready) {
+                Timed t(c, "clear");
+                HIPCHK(c, launch_clear_touched(c->dim, c->grid[cur], c->flags(cur), c->sp.nblocks, st), "clear");
+                c->p2g_ready = false;
+            }
+            mpmq_status r = do_sort(c);
+            if (r != MPMQ_OK) return r;
+            c->sorted = true;
+            c->sorted_at = s;
+        }
+        if (!c->p2g_ready) {
+            Timed t(c, "p2g");
+            HIPCHK(c, launch_p2g(c->dim, c->wm, c->ds, c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+                                 c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st), "p2g");
+        }
+        {
+            Timed t(c, "grid_update");
+            HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[cur], c->grid[nxt], c->flags(cur), c->flags(nxt),
+                                         c->sp.nblocks, c->stats(), st), "grid update");
+        }
+        const bool next_sorts = S > 0 && ((s + 1) % S) == 0;
+        {
+            Timed t(c, "substep");
+            HIPCHK(c, launch_substep(c->dim, c->wm, c->ds, c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+                                     c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
+                                     next_sorts ? 0 : 1, 1, c->stats(), st), "substep");
+        }
+        c->p2g_ready = !next_sorts;
+        c->step = s + 1;
+        c->steps_taken += 1;
+    }
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_step_count(mpmq_ctx *c, int64_t *out) {
+    if (!c || !out) return fail(c, MPMQ_EINVAL, "ctx or out is NULL");
+    *out = c->step;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_stats(mpmq_ctx *c, mpmq_stats_t *out) {
+    if (!c || !out) return fail(c, MPMQ_EINVAL, "ctx or out is NULL");
+    uint64_t h[ST_COUNT];
+    HIPCHK(c, hipMemcpyAsync(h, c->stats(), sizeof(h), hipMemcpyDeviceToHost, c->stream), "stats");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "stats");
+    for (int f = 0; f < 4; ++f) {
+        out->sat[f] = (int64_t)h[ST_SAT + f];
+        out->nan[f] = (int64_t)h[ST_NAN + f];
+        out->up[f] = (int64_t)h[ST_UP + f];
+        out->down[f] = (int64_t)h[ST_DOWN + f];
+    }
+    out->steps = c->steps_taken;
+    out->sorts = c->sorts;
+    out->fallback = (int64_t)h[ST_FALLBACK];
+    out->active_nodes = (int64_t)h[ST_ACTIVE];
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_reset_stats(mpmq_ctx *c) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(c->stats()), 0u, 2 * ST_COUNT, c->stream), "reset stats");
+    c->steps_taken = 0;
+    c->sorts = 0;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_set_timing(mpmq_ctx *c, int32_t enable) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_kernel_times(mpmq_ctx *c, mpmq_kernel_time *out, int32_t max, int32_t *count) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "kernel times");
+    for (auto &ev : c->events) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, ev.a, ev.b), "kernel times");
+        auto &slot = c->times[ev.name];
+        slot.first += 1;
+        slot.second += ms;
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+    }
+    c->events.clear();
+    int32_t i = 0;
+    for (auto &kv : c->times) {
+        if (out && i < max) {
+            std::memset(out[i].name, 0, sizeof(out[i].name));
+            std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = kv.second.first;
+            out[i].total_ms = kv.second.second;
+        }
+        ++i;
+    }
+    if (count) *count = i;
+    if (max < 0) c->times.clear();
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *, double *, double *) {
+    return fail(c, MPMQ_ENOTIMPL, "adjoint is not provided by this build");
+}
+
+}  // extern "C"

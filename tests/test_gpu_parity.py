@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bars: packed words bit-exact for the codec on identical float32 inputs and
+for config c1 (whose closed form has a margin of 0.0108 LSB at every
+rounding); positions within 1e-4 of the unit domain for dithered scenes,
+where FP32 arithmetic on the GPU may flip a rounding that lies within FP32
+error of a lattice tie.
+"""
+import numpy as np
+import pytest
+
+import workloads as WL
+from gpu_common import by_id, gpu_context, gpu_decode_np, note, oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+
+def edge_state(rng, dim, n):
+    x, v, C, F = WL.random_state(rng, dim, n)
+    # out-of-range, ties, denormals, NaN / Inf, exact lattice points
+    k = min(n, 16)
+    x[0, :k] = np.array([0.0, 1.0, 1.5, -0.1, 0.5, 2.0 ** -21, 1e-40, np.nan,
+                         0.25 + 2.0 ** -21, 3 * 2.0 ** -22, 0.999999, 0.7, 0.1, 0.2, 0.3, 0.4],
+                        dtype=np.float32)[:k]
+    v[0, :k] = np.array([25.0, -25.0, np.inf, -np.inf, 0.0, -0.0, 19.9999, 40.0 / 2 ** 17,
+                         1e-30, -1e-30, 7.0, -7.0, 3.0, 2.0, 1.0, 0.5], dtype=np.float32)[:k]
+    C[0, :k] = 100.0
+    F[0, :k] = 3.0
+    return x, v, C, F
+
+
+SCHEMES = {
+    "c1_2d": lambda: WL.scheme_c1(2, False, 1),
+    "c2_3d_dither": lambda: WL.scheme_c1(3, True, 5),
+    "c3_sexp": lambda: WL.scheme_c3(11),
+    "fp32_3d": lambda: WL.scheme_fp32(3, 0),
+    "fp32_2d": lambda: WL.scheme_fp32(2, 0),
+}
+
+
+@pytest.mark.parametrize("name", list(SCHEMES))
+@pytest.mark.parametrize("n", [1, 300, 5003])
+def test_encode_decode_bit_exact(gpu_lib, orc, name, n):
+    note(f"encode/decode {name} n={n}")
+    scheme = SCHEMES[name]()
+    dim = scheme["dim"]
+    rng = np.random.default_rng(n)
+    state = edge_state(rng, dim, n)
+    scene = {"scheme": scheme, "params": WL.params(dim, 64, 1e-4, 1e-6), "state": state}
+    ctx = gpu_context(gpu_lib, scene)
+    gw = ctx.words()
+    ow, ost = orc.encode(scheme, *state, 0, 2)
+    assert gw.shape == ow.shape
+    assert np.array_equal(gw, ow), f"{np.sum(gw != ow)} words differ"
+    gst = ctx.stats()
+    for f in "xvCF":
+        assert gst[f] == ost[f], f
+    # decode: binary64 value rounded once to float32
+    dec = gpu_decode_np(ctx)
+    odec = orc.decode(scheme, ow)
+    for g, o in zip(dec, odec):
+        o32 = o.astype(np.float32).astype(np.float64)
+        bad = int(np.sum(~((g == o32) | (np.isnan(g) & np.isnan(o32)))))
+        assert bad == 0, f"{bad} decoded values differ"
+    ctx.close()
+
+
+def test_encode_random_schemes(gpu_lib, orc):
+    rng = np.random.default_rng(42)
+    for trial in range(12):
+        dim = 2 + trial % 2
+        scheme = WL.random_scheme(rng, dim, seed=trial)
+        note(f"random scheme {trial}: {[(f['field'], f['kind'], f['bits']) for f in scheme['fields']]}")
+        state = WL.random_state(rng, dim, 2000)
+        scene = {"scheme": scheme, "params": WL.params(dim, 64, 1e-4, 1e-6), "state": state}
+        ctx = gpu_context(gpu_lib, scene)
+        ow, _ = orc.encode(scheme, *state, 0, 2)
+        assert np.array_equal(ctx.words(), ow)
+        ctx.close()
+
+
+def c1_codes(words, off, bits):
+    w = words.astype(np.uint64)
+    lo = w[off // 32]
+    hi = w[off // 32 + 1] if off // 32 + 1 < w.shape[0] else np.zeros_like(lo)
+    return (((lo | (hi << np.uint64(32))) >> np.uint64(off % 32)) & np.uint64((1 << bits) - 1)).astype(np.int64)
+
+
+def test_c1_closed_form_bit_exact(gpu_lib, orc):
+    """Config c1, 50 steps: GPU words equal the oracle's and the closed form."""
+    note("c1 50 steps")
+    sc = WL.c1()
+    ctx = gpu_context(gpu_lib, sc)
+    w0 = ctx.words()
+    ctx.step(50)
+    gw, gids = ctx.words(), ctx.ids()
+    sim, ow0, _ = oracle_sim(orc, sc)
+    assert np.array_equal(w0, ow0)
+    sim.step(50)
+    ow, oids = sim.words(), sim.ids()
+    assert np.array_equal(gids, oids)  # same sort permutation
+    assert np.array_equal(gw, ow)
+    # closed form: x (20 bits at 0, 20), v (16 at 40, 56), C (64..), F (128..)
+    assert np.all(c1_codes(gw, 56, 16) == 32768 - 100)
+    assert np.all(c1_codes(gw, 40, 16) == 32768)
+    assert np.array_equal(c1_codes(gw, 20, 20), c1_codes(w0, 20, 20)[gids] - 161)
+    assert np.array_equal(c1_codes(gw, 0, 20), c1_codes(w0, 0, 20)[gids])
+    for c in range(8):
+        assert np.all(c1_codes(gw, 72 + 16 * c, 16) == 32768)
+    st = ctx.stats()
+    assert st["fallback"] == 0 and st["sorts"] == 1 and st["steps"] == 50
+    ctx.close()
+
+
+def small_scene(dim, seed, dither=True, sort_every=4, n_extra=1234):
+    """Two cubes with different velocities plus a ragged cloud, 32^dim grid."""
+    rng = np.random.default_rng(seed)
+    res = 32
+    side = 10 / res
+    corners = np.array([[0.2, 0.3, 0.25], [0.55, 0.35, 0.5]])[:, :dim]
+    vels = rng.uniform(-1, 1, (2, dim))
+    counts = [int(8 * 10 ** dim * 0.9), int(8 * 10 ** dim * 0.9)]
+    sch = WL.scheme_c1(dim, dither, seed)
+    sc = WL.cubes_scene("small", seed, res, corners, side, counts, vels, 5e-4, 20, sch, sort_every, dim=dim)
+    x, v, C, F = sc["state"]
+    xe = rng.uniform(0.15, 0.85, (dim, n_extra)).astype(np.float32)
+    ve = rng.uniform(-0.5, 0.5, (dim, n_extra)).astype(np.float32)
+    _, Ce, Fe = WL.rest_state(dim, n_extra)
+    sc["state"] = (np.concatenate([x, xe], 1), np.concatenate([v, ve], 1), np.concatenate([C, Ce], 1),
+                   np.concatenate([F, Fe], 1))
+    sc["n"] = sc["state"][0].shape[1]
+    return sc
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dither", [False, True])
+def test_small_scene_trajectory(gpu_lib, orc, dim, dither):
+    sc = small_scene(dim, 3 + dim, dither)
+    steps = 20
+    note(f"small scene dim={dim} dither={dither} n={sc['n']} steps={steps}")
+    ctx = gpu_context(gpu_lib, sc)
+    sim, ow0, _ = oracle_sim(orc, sc)
+    assert np.array_equal(ctx.words(), ow0)
+    for chunk in (1, 9, 10):
+        ctx.step(chunk)
+        sim.step(chunk)
+        if chunk == 1:
+            # after one substep only roundings within FP32 error of a tie differ
+            same = np.mean(by_id(ctx.words(), ctx.ids()) == by_id(sim.words(), sim.ids()))
+            assert same > 0.9, same
+        gx, gv, gC, gF = gpu_decode_np(ctx)
+        gids = ctx.ids()
+        ox, ov, oC, oF = orc.decode(sc["scheme"], sim.words())
+        oids = sim.ids()
+        gx, ox = by_id(gx, gids), by_id(ox, oids)
+        err = np.max(np.abs(gx - ox))
+        assert err <= 1e-4, err
+        gv, ov = by_id(gv, gids), by_id(ov, oids)
+        assert np.max(np.abs(gv - ov)) <= 0.05
+    st = ctx.stats()
+    assert st["steps"] == steps and st["sorts"] == 5
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_grid_mass_conservation(gpu_lib, dim):
+    import torch
+    sc = small_scene(dim, 11, True, 0)
+    note(f"grid mass dim={dim}")
+    ctx = gpu_context(gpu_lib, sc)
+    ctx.step(3)
+    ctx.stream.synchronize()
+    m_p = sc["params"]["rho"] * sc["params"]["p_vol"]
+    s = ctx.step_count()
+    g = (ctx.grid_a if s % 2 == 0 else ctx.grid_b).view(torch.float32).view(-1, 4).double()
+    mass = g[:, dim].sum().item()
+    assert abs(mass - m_p * sc["n"]) <= 1e-5 * m_p * sc["n"]
+    ctx.close()
+
+
+def test_empty_and_resume(gpu_lib, orc):
+    note("empty scene, resume")
+    sc = WL.c1()
+    empty = dict(sc, state=tuple(a[:, :0] for a in sc["state"]))
+    ctx = gpu_context(gpu_lib, empty, capacity=16)
+    ctx.step(3)
+    assert ctx.step_count() == 3
+    ctx.close()
+    sc["scheme"] = WL.scheme_c1(2, True, 9)
+    sc["params"]["sort_every"] = 8
+    a = gpu_context(gpu_lib, sc)
+    a.step(20)
+    b = gpu_context(gpu_lib, sc)
+    b.step(7)
+    b.step(13)
+    xa = by_id(gpu_decode_np(a)[0], a.ids())
+    xb = by_id(gpu_decode_np(b)[0], b.ids())
+    assert np.max(np.abs(xa - xb)) <= 1e-5
+    a.close()
+    b.close()
+
+
+def test_step_before_encode_is_state_error(gpu_lib):
+    sc = WL.c1()
+    ctx = gpu_lib.Context(sc["scheme"], sc["params"], 100)
+    with pytest.raises(gpu_lib.MpmqError) as e:
+        ctx.step(1)
+    assert e.value.status == -4
+    with pytest.raises(gpu_lib.MpmqError) as e:
+        ctx.adjoint()
+    assert e.value.status == -5
+    ctx.close()
