@@ -1,0 +1,288 @@
+"""Benchmark of the quantized MLS-MPM substep on one MI355X.
+
+Metric: particle-substeps/s and bytes/particle, quantized vs the float32
+layout, for the 3D elastic workload of 3e8 particles (186 cubes of 60^3
+cells in a 512^3 grid, dt = 1e-4; x 3x21-bit fixed, v 3x13-bit
+shared-exponent, C 9x16-bit, F 9x14-bit, all dithered: 48 B per particle
+against 96 B for float32).  A step is one full substep of the hot path
+(P2G, grid update, G2P, dithered re-encode and store), with the packed
+state resident in HBM; the particle sort runs once at set-up (during the
+warm-up) and its time is reported separately.
+
+Prints one JSON line on stdout; progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--config c3|c2|c1]
+                  [--no-fp32] [--no-cpu] [--only quant|fp32]
+  python bench.py --calib-copy   # plain copy of known size (counter calibration)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-substeps/s and bytes/particle, quantized vs FP32 layout, at 1e-4 pos error"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2207_04658_amd/csrc/kernels.hip", "paper_2207_04658_amd/csrc/mpmq_device.hpp",
+                  "paper_2207_04658_amd/csrc/mpmq_internal.hpp"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(config):
+    """HBM bytes per substep launch from the committed rocprofv3 counter
+    summary, if it was taken with the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"substep_{config}_counters.md")
+    if not os.path.exists(path):
+        return None, None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes:
+        return None, None
+    if m_hash.group(1) != kernel_hash():
+        return None, "stale"
+    return float(m_bytes.group(1)), "ok"
+
+
+# ----------------------------------------------------------------------------- scenes
+def build_scene(config, device):
+    """Returns (scene dict without host state, device SoA tensors x, v, C, F)."""
+    import numpy as np
+    import torch
+    import workloads as WL
+
+    if config == "c3":
+        lay = WL.c3_layout()
+        n = sum(lay["counts"])
+        params = WL.c3_params()
+        scheme = WL.scheme_c3()
+        x = torch.empty((3, n), dtype=torch.float32, device=device)
+        v = torch.empty((3, n), dtype=torch.float32, device=device)
+        off = 0
+        t0 = time.time()
+        for i in range(len(lay["counts"])):
+            xi, vi = WL.cube_particles(0, i, lay["corners"][i], lay["side"], lay["counts"][i], lay["vels"][i])
+            c = xi.shape[1]
+            x[:, off:off + c].copy_(torch.from_numpy(xi))
+            v[:, off:off + c].copy_(torch.from_numpy(vi))
+            off += c
+            if i % 40 == 0:
+                log(f"generated cube {i}/{len(lay['counts'])} ({time.time() - t0:.1f}s)")
+        desc = ("3D MLS-MPM elastic, 300M particles in 186 cubes of 60^3 cells, 512^3 grid, dt=1e-4, "
+                "fixed-corotated E=1e3 nu=0.2; x 3x21b fixed, v 3x13b shared-exp (6b), C 9x16b, F 9x14b, dithered")
+        scene = {"name": "c3", "scheme": scheme, "params": params, "n": n, "desc": desc, "grid": 512,
+                 "steps_cfg": 10}
+    else:
+        sc = WL.c2() if config == "c2" else WL.c1()
+        xh, vh, _, _ = sc["state"]
+        n = sc["n"]
+        x = torch.from_numpy(xh).to(device)
+        v = torch.from_numpy(vh).to(device)
+        desc = {"c2": "3D MLS-MPM elastic, 2^20 particles in 4 cubes, 128^3 grid, dt=2e-4, 52 B/particle dithered",
+                "c1": "2D MLS-MPM elastic block, 8192 particles, 128^2 grid, dt=1e-4, 28 B/particle"}[config]
+        scene = {"name": config, "scheme": sc["scheme"], "params": sc["params"], "n": n, "desc": desc,
+                 "grid": sc["params"]["grid_res"], "steps_cfg": sc["steps"]}
+    dim = scene["params"]["dim"]
+    C = torch.zeros((dim * dim, n), dtype=torch.float32, device=device)
+    F = torch.zeros((dim * dim, n), dtype=torch.float32, device=device)
+    for a in range(dim):
+        F[a * dim + a].fill_(1.0)
+    return scene, (x, v, C, F)
+
+
+def run_layout(mq, scene, scheme, state, steps, warmup, label):
+    import torch
+    n = scene["n"]
+    ctx = mq.Context(scheme, scene["params"], n, track_ids=False)
+    sz = ctx.sizes
+    log(f"{label}: W={sz['words_per_particle']} words, state {sz['packed_bytes'] / 1e9:.2f} GB, "
+        f"scratch {sz['scratch_bytes'] / 1e9:.2f} GB, grid 2x{sz['grid_bytes'] / 1e9:.2f} GB")
+    ctx.encode(*state)
+    ctx.set_timing(True)
+    ctx.step(warmup)  # includes the set-up sort
+    warm = ctx.kernel_times()
+    ctx.kernel_times(clear=True)
+    sort_ms = warm.get("sort", (0, 0.0))[1]
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    log(f"{label}: warm-up done (sort {sort_ms:.1f} ms); timing {steps} steps")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(ctx.stream)
+    ctx.step(steps)
+    stop.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    kt = ctx.kernel_times()
+    st = ctx.stats()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    per_step = ms / max(steps, 1)
+    log(f"{label}: {per_step:.3f} ms/step, kernels " +
+        ", ".join(f"{k}={v[1] / max(v[0], 1):.3f}ms" for k, v in kt.items()))
+    return {"ms_per_step": per_step, "value": n * steps / (ms / 1e3) if ms > 0 else 0.0,
+            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()},
+            "sort_ms": sort_ms, "stats": st, "W": sz["words_per_particle"],
+            "bytes_per_particle": 4 * sz["words_per_particle"],
+            "footprint_bytes": sz["packed_bytes"] + 2 * sz["grid_bytes"] + sz["scratch_bytes"]}
+
+
+def roofline(res, n, steps):
+    """Algorithmic HBM bytes of one fused substep launch over its measured
+    average duration: 8W bytes per particle (packed state read + written once)
+    plus 32 bytes per active grid node (velocity gathered once, momentum and
+    mass scattered once)."""
+    k = res["kernels"].get("substep")
+    if not k:
+        return None
+    active = res["stats"]["active_nodes"] / max(steps, 1)
+    algo = 8.0 * res["W"] * n + 32.0 * active
+    achieved = algo / (k["avg_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_substep",
+            "algorithmic_bytes_per_launch": algo, "avg_launch_ms": k["avg_ms"],
+            "active_nodes_per_step": active}
+
+
+def cpu_baseline(scene):
+    """The oracle (FP64, single thread) on a bounded sample of the workload."""
+    import numpy as np
+    import oracle
+    import workloads as WL
+    if scene["name"] == "c3":
+        sub = WL.c3(only=[0])
+        sample = (f"cube 0 of 186 ({sub['n']} particles) on the full 512^3 grid, 1 substep after a "
+                  f"warm-up substep that includes the sort")
+    elif scene["name"] == "c2":
+        sub = WL.c2(cubes=1)
+        sample = f"cube 0 of 4 ({sub['n']} particles) on the 128^3 grid, 1 substep after a warm-up substep"
+    else:
+        sub = WL.c1()
+        sample = "the full scene (8192 particles), 1 substep after a warm-up substep"
+    x, v, C, F = sub["state"]
+    words, _ = oracle.encode(sub["scheme"], x, v, C, F, 0, 2)
+    sim = oracle.Sim(sub["scheme"], sub["params"], words)
+    sim.step(1)
+    t0 = time.perf_counter()
+    sim.step(1)
+    dt = time.perf_counter() - t0
+    sim.close()
+    return {"value": sub["n"] / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "seconds": round(dt, 3)}
+
+
+def calib_copy():
+    import torch
+    nbytes = 4 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": nbytes}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["quant", "fp32"], default=None)
+    ap.add_argument("--calib-copy", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X: this build has no multi-GPU path (the design for "
+              "sharding by spatial slabs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if a.calib_copy:
+        calib_copy()
+        return
+    import torch
+    import paper_2207_04658_amd as mq
+    import workloads as WL
+    mq.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    scene, state = build_scene(a.config, dev)
+    n = scene["n"]
+    log(f"scene {scene['name']}: {n} particles")
+    out = {}
+    if a.only in (None, "quant"):
+        out["quant"] = run_layout(mq, scene, scene["scheme"], state, a.steps, a.warmup, "quantized")
+    if a.only == "fp32" or (a.only is None and not a.no_fp32):
+        out["fp32"] = run_layout(mq, scene, WL.scheme_fp32(scene["params"]["dim"]), state, a.steps, a.warmup,
+                                 "fp32 layout")
+    del state
+    torch.cuda.empty_cache()
+    main_res = out.get("quant") or out["fp32"]
+    rf = roofline(main_res, n, a.steps)
+    traffic, tstate = read_traffic(scene["name"])
+    if rf is not None:
+        rf["traffic"] = traffic
+        rf["traffic_status"] = tstate or "no counter summary"
+    cpu = None
+    if not a.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(scene)
+        log(f"cpu baseline {cpu['value']:.3g} particle-substeps/s in {cpu['seconds']} s")
+    q, f = out.get("quant"), out.get("fp32")
+    line = {
+        "metric": METRIC,
+        "value": round(main_res["value"], 1),
+        "unit": "particle-substeps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": scene["desc"], "particles": n, "grid": scene["grid"],
+                   "layout": "quantized" if q else "fp32"},
+        "bytes_per_particle": main_res["bytes_per_particle"],
+        "footprint_bytes_per_particle": round(main_res["footprint_bytes"] / n, 2),
+        "sort_ms": round(main_res["sort_ms"], 3),
+        "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in main_res["kernels"].items()},
+        "roofline": rf,
+        "cpu_baseline": cpu,
+    }
+    if q and f:
+        line["fp32_layout"] = {"value": round(f["value"], 1), "ms_per_step": round(f["ms_per_step"], 4),
+                               "bytes_per_particle": f["bytes_per_particle"],
+                               "footprint_bytes_per_particle": round(f["footprint_bytes"] / n, 2),
+                               "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in f["kernels"].items()}}
+        line["speedup_vs_fp32"] = round(q["value"] / f["value"], 4)
+        line["compression_vs_fp32"] = round(f["bytes_per_particle"] / q["bytes_per_particle"], 4)
+        line["fp32_roofline"] = roofline(f, n, a.steps)
+    line["saturations"] = {k: main_res["stats"][k]["sat"] for k in "xvCF"}
+    line["nan"] = {k: main_res["stats"][k]["nan"] for k in "xvCF"}
+    line["fallback_stencils"] = main_res["stats"]["fallback"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
