@@ -141,7 +141,7 @@ mpmq_status mpmq_query_sizes(const mpmq_scheme *scheme, const mpmq_params *param
 
 /* Creates a context over caller buffers; `hip_stream` is a hipStream_t
  * (NULL = default stream).  Clears the grid buffers and scratch on the
- * stream.  EINVAL / ENOMEM (capacity < 1 or > 2^31-256) / EDEVICE. */
+ * stream.  EINVAL / ENOMEM (capacity < 1 or > 2^30-256) / EDEVICE. */
 mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params,
                         const mpmq_buffers *buffers, int64_t capacity, void *hip_stream,
                         mpmq_ctx **out);
@@ -173,6 +173,12 @@ mpmq_status mpmq_step(mpmq_ctx *ctx, int32_t n_substeps);
 
 /* Substep counter (the Philox "step" of the next substep). */
 mpmq_status mpmq_step_count(mpmq_ctx *ctx, int64_t *out);
+
+/* Encoder statistics collected by mpmq_step: level 0 (default) counts
+ * saturations and NaN inputs; level 1 also counts round-ups and
+ * round-downs per field (the dithering diagnostic of Sec. 8.1), at a small
+ * cost per stored component.  mpmq_encode always counts all four. */
+mpmq_status mpmq_set_stats(mpmq_ctx *ctx, int32_t level);
 
 /* Accumulated statistics.  Synchronizes the stream. */
 mpmq_status mpmq_stats(mpmq_ctx *ctx, mpmq_stats_t *out);

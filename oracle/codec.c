@@ -19,9 +19,11 @@
  *    saturate to [0, 2^b-1] and are counted.
  *  - Dither (Eq. 11): round(t + xi), xi ~ U(-1/2, 1/2), is floor(t + xi')
  *    with xi' ~ U(0,1); xi' = (r + 1/2) * 2^-16 for a 16-bit Philox draw r.
- *  - Philox counter = (slot, step, group, tag), key = seed; component k of
- *    the record (placement order, magnitudes only) takes 16-bit half k%2 of
- *    output word (k%8)/2 of group k/8.
+ *  - Philox counter = (slot, step, group, tag), key = seed.  Components are
+ *    numbered in the canonical order x, v, C, F (matrices row-major,
+ *    independent of the placement order): component k takes 16-bit half k%2
+ *    of output word (k%8)/2 of group k/8.  A shared-exponent field draws for
+ *    its magnitudes only.
  *  - Shared exponent (the custom float type mentioned with the hand-written
  *    scheme comparison, Sec. 8.1): E_max = ceil(log2 hi),
  *    E_min = E_max - 2^e + 1, E = clamp(ilogb(max|v_k|) + 1, E_min, E_max)
@@ -264,13 +266,14 @@ static void encode_record(const orc_scheme *s, const double vals[4][9], uint32_t
     int dim = s->dim;
     memset(rec, 0, sizeof(uint32_t) * (size_t)W);
     int off = 0;
-    int k = 0; /* magnitude component index, placement order */
     double draws[32];
     dither_draws(s->seed, slot, step, tag, 2 * dim + 2 * dim * dim, draws);
     for (int i = 0; i < 4; ++i) {
         const orc_field *f = &s->f[i];
         int nc = ncomp_of(f->field, dim);
         orc_stat *st = stats ? &stats[f->field] : 0;
+        /* canonical index of the field's first component: x, v, C, F */
+        int k = f->field == ORC_X ? 0 : f->field == ORC_V ? dim : f->field == ORC_C ? 2 * dim : 2 * dim + dim * dim;
         double rel[9];
         for (int c = 0; c < nc; ++c) {
             double val = vals[f->field][c];
@@ -298,7 +301,6 @@ static void encode_record(const orc_scheme *s, const double vals[4][9], uint32_t
                 off += f->bits;
             }
         }
-        k += nc;
     }
 }
 

@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         "mpmq_step_count": [P, ct.POINTER(ct.c_int64)],
         "mpmq_stats": [P, ct.POINTER(mpmq_stats_t)],
         "mpmq_reset_stats": [P],
+        "mpmq_set_stats": [P, ct.c_int32],
         "mpmq_set_timing": [P, ct.c_int32],
         "mpmq_kernel_times": [P, ct.POINTER(mpmq_kernel_time), ct.c_int32, ct.POINTER(ct.c_int32)],
         "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, P],
@@ -122,7 +123,7 @@ def load(path: str = LIB_PATH):
 
 def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
-            "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats",
+            "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
             "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint", "mpmq_error_string",
             "mpmq_last_error"]
 
@@ -270,6 +271,10 @@ class Context:
                for i in range(4)}
         out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes)
         return out
+
+    def set_stats(self, level):
+        """0: saturation and NaN counts (default); 1: also round-up/down counts."""
+        _check(load().mpmq_set_stats(self._h, int(level)), self._h)
 
     def reset_stats(self):
         _check(load().mpmq_reset_stats(self._h), self._h)

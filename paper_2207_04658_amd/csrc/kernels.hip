@@ -2,9 +2,11 @@
 //
 // Data layout in HBM:
 //   packed state  uint32 words[W][cap]          word-major SoA, coalesced
-//   grid          float4 node[nblocks][BLK^dim]  (mom_x, mom_y, mom_z | mass)
-//                 block-major; two buffers (this step's P2G target and the
-//                 previous one), plus one "touched" flag per node block each
+//   grid          GNode node[nblocks][BLK^dim], 32 B: int64 fixed-point
+//                 momentum xyz + mass during P2G, float4 velocity|mass after
+//                 the grid update; block-major; two buffers (this step's P2G
+//                 target and the previous one), plus one "touched" flag per
+//                 node block each
 //   work items    (block, p0, p1): a sorted block's particles, split in
 //                 chunks of at most item_cap
 #include "mpmq_device.hpp"
@@ -67,53 +69,56 @@ static int grid_for(int64_t n, int per_block = 256) {
 // ---------------------------------------------------------------------------
 // encode / decode (float32 SoA <-> packed words)
 // ---------------------------------------------------------------------------
-template <int DIM, int WM>
-__global__ __launch_bounds__(WG) void k_encode(DevScheme s, const float *__restrict__ x,
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_encode(const DevScheme *__restrict__ sch, const float *__restrict__ x,
                                                const float *__restrict__ v, const float *__restrict__ C,
                                                const float *__restrict__ F, int64_t n, int64_t cap,
-                                               uint32_t *__restrict__ words, uint32_t *__restrict__ ids,
+                                               uint32_t *words, uint32_t *__restrict__ ids,
                                                uint32_t step, uint32_t tag, uint64_t *stats) {
     constexpr int D2 = DIM * DIM;
     LaneStats ls;
     ls.clear();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p < n) {
-        double xv[DIM], vv[DIM], Cv[D2], Fv[D2];
+        double xv[DIM], qx[DIM];
+        float vv[DIM], Cv[D2], Fv[D2], qv[DIM], qC[D2], qF[D2];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             xv[c] = (double)x[c * n + p];
-            vv[c] = (double)v[c * n + p];
+            vv[c] = v[c * n + p];
         }
 #pragma unroll
         for (int c = 0; c < D2; ++c) {
-            Cv[c] = (double)C[c * n + p];
-            Fv[c] = (double)F[c * n + p];
+            Cv[c] = C[c * n + p];
+            Fv[c] = F[c * n + p];
         }
-        const uvec<16> rnd = dither_draws(s, (uint32_t)p, step, tag);
-        uvec<WM> w = 0;
-        enc_field<DIM, DIM>(s, 0, xv, rnd, w, ls);
-        enc_field<DIM, DIM>(s, 1, vv, rnd, w, ls);
-        enc_field<DIM, D2>(s, 2, Cv, rnd, w, ls);
-        enc_field<DIM, D2>(s, 3, Fv, rnd, w, ls);
-        store_record<WM>(words, s.W, cap, p, w);
+        const Draws rnd = dither_draws(scheme_ref(sch), (uint32_t)p, step, tag);
+        OutStream os{words, cap, (uint32_t)p * 4u, 0ull, 0, 0};
+        encode_record<DIM, true>(sch, xv, vv, Cv, Fv, rnd, os, ls, qx, qv, qC, qF);
         if (ids) ids[p] = (uint32_t)p;
     }
     flush_stats(ls, stats);
 }
 
-template <int DIM, int WM>
-__global__ __launch_bounds__(WG) void k_decode(DevScheme s, const uint32_t *__restrict__ words, int64_t n,
+template <int DIM, typename T>
+__device__ __forceinline__ void decode_all(const DevScheme *sp, const uint32_t *words, int64_t cap, uint32_t p4,
+                                           double *xv, T *vv, T *Cv, T *Fv) {
+    SchemeRef s = scheme_ref(sp);
+    dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xv);
+    dec_field<DIM, 1, T>(&s->f[1], words, cap, p4, vv);
+    dec_field<DIM, 2, T>(&s->f[2], words, cap, p4, Cv);
+    dec_field<DIM, 3, T>(&s->f[3], words, cap, p4, Fv);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_decode(const DevScheme *__restrict__ sch, const uint32_t *__restrict__ words, int64_t n,
                                                int64_t cap, float *__restrict__ x, float *__restrict__ v,
                                                float *__restrict__ C, float *__restrict__ F) {
     constexpr int D2 = DIM * DIM;
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p >= n) return;
-    const uvec<WM> w = load_record<WM>(words, s.W, cap, p);
     double xv[DIM], vv[DIM], Cv[D2], Fv[D2];
-    dec_field<DIM, DIM>(s, 0, w, xv);
-    dec_field<DIM, DIM>(s, 1, w, vv);
-    dec_field<DIM, D2>(s, 2, w, Cv);
-    dec_field<DIM, D2>(s, 3, w, Fv);
+    decode_all<DIM, double>(sch, words, cap, (uint32_t)p * 4u, xv, vv, Cv, Fv);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         if (x) x[c * n + p] = (float)xv[c];
@@ -130,16 +135,15 @@ __global__ __launch_bounds__(WG) void k_decode(DevScheme s, const uint32_t *__re
 // particle sort by cell
 // key = block * BLK^dim + cell-in-block of the (clamped) base cell
 // ---------------------------------------------------------------------------
-template <int DIM, int WM>
-__global__ __launch_bounds__(WG) void k_sort_keys(DevScheme s, DevParams P, const uint32_t *__restrict__ words,
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_sort_keys(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
                                                   int64_t n, int64_t cap, uint32_t *__restrict__ keys,
                                                   uint32_t *__restrict__ vals, uint32_t *__restrict__ cell_count) {
     constexpr int B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p >= n) return;
-    const uvec<WM> w = load_record<WM>(words, s.W, cap, p);
     double xv[DIM];
-    dec_field<DIM, DIM>(s, 0, w, xv);
+    dec_field<DIM, 0, double>(&scheme_ref(sch)->f[0], words, cap, (uint32_t)p * 4u, xv);
     int base[DIM];
     float fx[DIM];
     stencil_base<DIM>(xv, P.inv_dx_d, P.res, base, fx);
@@ -370,24 +374,73 @@ __global__ __launch_bounds__(WG) void k_items(const uint32_t *__restrict__ cell_
     }
 }
 
+// Fixed-point conversion: round(v * 2^32) as two's complement int64 for
+// |v| < 2^19, via binary64: fma(w, x, 1.5*2^52) puts the rounded integer in
+// the low mantissa bits (exponent field constant), the subtraction removes
+// the offset.  w * x carries the 2^32 scale already.
+__device__ __forceinline__ unsigned long long fixp(double w, double xs) {
+    return (unsigned long long)__double_as_longlong(fma(w, xs, FIX_MAGIC)) - FIX_MAGIC_BITS;
+}
+
+// P2G straight into the grid buffer, for a particle whose stencil left its tile.
+template <int DIM>
+__device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, const double (*w)[3],
+                                           const double *q, const double (*ac)[DIM], GNode *__restrict__ gout,
+                                           uint32_t *__restrict__ flags) {
+    constexpr int NST = Geo<DIM>::NST;
+#pragma unroll
+    for (int s = 0; s < NST; ++s) {
+        const int o[3] = {s % 3, (s / 3) % 3, s / 9};
+        int ijk[DIM];
+        double wt = 1.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            wt *= w[a][o[a]];
+        }
+        unsigned long long *g = gout[node_index<DIM>(ijk, P.nb)].q;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double val = q[a];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) val += ac[b][a] * (double)o[b];
+            atomicAdd(g + a, fixp(wt, val));
+        }
+        atomicAdd(g + 3, fixp(wt, FIX_ONE));
+        flags[block_of<DIM>(ijk, P.nb)] = 1u;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// P2G of one particle from its decoded (quantized) state
+// P2G of one particle from its decoded (quantized) state.  Node i receives,
+// per unit particle mass, w_i (v + (A/m)(x_i - x_p)) and w_i, accumulated as
+// exact 64-bit fixed point (LDS integer atomics: float LDS atomics are an
+// order of magnitude slower on this part, and integer sums are
+// order-independent).
 // ---------------------------------------------------------------------------
 template <int DIM>
 __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
                                              const float *C, const float *F, const int *origin,
-                                             float *__restrict__ acc, float4 *__restrict__ gout,
+                                             unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
                                              uint32_t *__restrict__ flags, uint32_t &fallback) {
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
+    constexpr float LIM = 4096.0f;  // |q|, |a_b| <= 2^12 keeps every term below 2^19
     int base[DIM];
-    float fx[DIM], w[DIM][3];
+    float fx[DIM];
     stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
+    double w[DIM][3];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) bspline(fx[a], w[a]);
+    for (int a = 0; a < DIM; ++a) {
+        float wf[3];
+        bspline(fx[a], wf);
+        w[a][0] = wf[0];
+        w[a][1] = wf[1];
+        w[a][2] = wf[2];
+    }
     // fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + lambda J (J-1) I
     float R[D2];
     float J;
-    if (DIM == 2) {
+    if constexpr (DIM == 2) {
         polar2(F, R);
         J = F[0] * F[3] - F[1] * F[2];
     } else {
@@ -395,7 +448,8 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
         J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
             F[2] * (F[3] * F[7] - F[4] * F[6]);
     }
-    float A[D2];
+    // A / m_p = -4 dt / (rho dx^2) tau + C
+    float Am[D2];
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
@@ -404,19 +458,20 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
 #pragma unroll
             for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
             t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
-            A[i * DIM + j] = P.stress_coef * t + P.p_mass * C[i * DIM + j];
+            Am[i * DIM + j] = P.stress_over_m * t + C[i * DIM + j];
         }
-    // node contribution = w (m v + A (o - f) dx) = w (q + sum_b a_b o_b)
-    float q[DIM], ac[DIM][DIM];  // ac[b][a] = A[a][b] dx
+    // node value = w (q + sum_b a_b o_b), q = v - (A/m) f dx, a_b = (A/m)[:, b] dx, scaled by 2^32
+    double q[DIM], ac[DIM][DIM];  // ac[b][a]
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        float t = P.p_mass * v[a];
+        float t = v[a];
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            ac[b][a] = A[a * DIM + b] * P.dx;
-            t -= ac[b][a] * fx[b];
+            const float ab = fminf(fmaxf(Am[a * DIM + b] * P.dx, -LIM), LIM);
+            ac[b][a] = (double)ab * FIX_ONE;
+            t -= ab * fx[b];
         }
-        q[a] = t;
+        q[a] = (double)fminf(fmaxf(t, -LIM), LIM) * FIX_ONE;
     }
     bool in_tile = true;
     int l[DIM];
@@ -430,63 +485,45 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
         if constexpr (DIM == 3) {
 #pragma unroll
             for (int oz = 0; oz < 3; ++oz) {
+                double vz[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vz[a] = q[a] + ac[2][a] * (double)oz;
 #pragma unroll
                 for (int oy = 0; oy < 3; ++oy) {
-                    const float wzy = w[DIM - 1][oz] * w[1][oy];
+                    const double wzy = w[2][oz] * w[1][oy];
+                    double vzy[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) vzy[a] = vz[a] + ac[1][a] * (double)oy;
 #pragma unroll
                     for (int ox = 0; ox < 3; ++ox) {
-                        const float wt = wzy * w[0][ox];
+                        const double wt = wzy * w[0][ox];
                         const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            const float val = q[a] + ac[0][a] * ox + ac[1][a] * oy + ac[DIM - 1][a] * oz;
-                            atomicAdd(&acc[a * TN + idx], wt * val);
-                        }
-                        atomicAdd(&acc[DIM * TN + idx], wt * P.p_mass);
+                        for (int a = 0; a < 3; ++a)
+                            atomicAdd(&acc[a * TN + idx], fixp(wt, vzy[a] + ac[0][a] * (double)ox));
+                        atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
                     }
                 }
             }
         } else {
 #pragma unroll
             for (int oy = 0; oy < 3; ++oy) {
+                double vy[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) vy[a] = q[a] + ac[1][a] * (double)oy;
 #pragma unroll
                 for (int ox = 0; ox < 3; ++ox) {
-                    const float wt = w[1][oy] * w[0][ox];
+                    const double wt = w[1][oy] * w[0][ox];
                     const int idx = l0 + oy * TB + ox;
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        const float val = q[a] + ac[0][a] * ox + ac[1][a] * oy;
-                        atomicAdd(&acc[a * TN + idx], wt * val);
-                    }
-                    atomicAdd(&acc[DIM * TN + idx], wt * P.p_mass);
+                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, vy[a] + ac[0][a] * (double)ox));
+                    atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
                 }
             }
         }
     } else {
         fallback += 1;
-        constexpr int NST = Geo<DIM>::NST;
-        for (int s = 0; s < NST; ++s) {
-            const int o[3] = {s % 3, (s / 3) % 3, s / 9};
-            int ijk[DIM];
-            float wt = 1.0f;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                ijk[a] = base[a] + o[a];
-                wt *= w[a][o[a]];
-            }
-            float val[DIM];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                val[a] = q[a];
-#pragma unroll
-                for (int b = 0; b < DIM; ++b) val[a] += ac[b][a] * o[b];
-            }
-            float *g = reinterpret_cast<float *>(gout + node_index<DIM>(ijk, P.nb));
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) unsafeAtomicAdd(g + a, wt * val[a]);
-            unsafeAtomicAdd(g + DIM, wt * P.p_mass);
-            flags[block_of<DIM>(ijk, P.nb)] = 1u;
-        }
+        p2g_global<DIM>(P, base, w, q, ac, gout, flags);
     }
 }
 
@@ -520,62 +557,67 @@ __device__ __forceinline__ bool tile_node(int t, const int *origin, int res, int
 }
 
 template <int DIM>
-__device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin, const float *__restrict__ acc,
-                                           float4 *__restrict__ gout, uint32_t *__restrict__ flags) {
+__device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin,
+                                           const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
+                                           uint32_t *__restrict__ flags) {
     constexpr int TN = Geo<DIM>::TN;
     for (int t = threadIdx.x; t < TN; t += WG) {
-        const float m = acc[DIM * TN + t];
-        const float a0 = acc[t], a1 = acc[TN + t], a2 = (DIM == 3) ? acc[2 * TN + t] : 0.0f;
-        if (m != 0.0f || a0 != 0.0f || a1 != 0.0f || a2 != 0.0f) {
+        const unsigned long long a0 = acc[t], a1 = acc[TN + t], a2 = acc[2 * TN + t], m = acc[3 * TN + t];
+        if ((a0 | a1 | a2 | m) != 0ull) {
             int ijk[DIM];
             if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached: contributions stay in-grid
-            float *g = reinterpret_cast<float *>(gout + node_index<DIM>(ijk, P.nb));
-            unsafeAtomicAdd(g + 0, a0);
-            unsafeAtomicAdd(g + 1, a1);
-            if (DIM == 3) unsafeAtomicAdd(g + 2, a2);
-            unsafeAtomicAdd(g + DIM, m);
+            unsigned long long *g = gout[node_index<DIM>(ijk, P.nb)].q;
+            atomicAdd(g + 0, a0);
+            atomicAdd(g + 1, a1);
+            if (DIM == 3) atomicAdd(g + 2, a2);
+            atomicAdd(g + 3, m);
             flags[block_of<DIM>(ijk, P.nb)] = 1u;
         }
     }
 }
 
-// mass slot of a grid node: w in 3D, z in 2D
-template <int DIM> __device__ __forceinline__ float node_mass(const float4 &g) { return DIM == 3 ? g.w : g.z; }
+// ---------------------------------------------------------------------------
+// Persistent work-item walk.  Work-groups are dispatched round-robin over the
+// 8 XCDs (each with its own L2), so work-group b runs on XCD b % 8; XCD x
+// walks the contiguous range [x*chunk, (x+1)*chunk) of the block-ordered
+// items, so spatially adjacent tiles (which share halo nodes) meet in the
+// same L2.  The trip count depends only on blockIdx: uniform per group.
+// ---------------------------------------------------------------------------
+struct ItemWalk {
+    uint32_t first, stride, end;
+    __device__ ItemWalk(uint32_t nit) {
+        const uint32_t x = blockIdx.x & 7u, per = gridDim.x >> 3;
+        const uint32_t chunk = (nit + 7u) >> 3;
+        first = x * chunk + (blockIdx.x >> 3);
+        stride = per;
+        end = min(nit, (x + 1u) * chunk);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // bootstrap P2G from the packed state (after a sort or an encode)
 // ---------------------------------------------------------------------------
-template <int DIM, int WM>
-__global__ __launch_bounds__(WG) void k_p2g(DevScheme s, DevParams P, const uint32_t *__restrict__ words,
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_p2g(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
                                             int64_t cap, const WorkItem *__restrict__ items,
-                                            const uint32_t *__restrict__ n_items, float4 *__restrict__ gout,
+                                            const uint32_t *__restrict__ n_items, GNode *__restrict__ gout,
                                             uint32_t *__restrict__ flags, uint64_t *stats) {
     constexpr int TN = Geo<DIM>::TN, D2 = DIM * DIM;
-    __shared__ float acc[(DIM + 1) * TN];
+    __shared__ unsigned long long acc[4 * TN];
     const uint32_t nit = *n_items;
     uint32_t fallback = 0;
-    for (uint32_t item = blockIdx.x; item < nit; item += gridDim.x) {
+    const ItemWalk walk(nit);
+    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
         const WorkItem it = items[item];
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
-        for (int t = threadIdx.x; t < (DIM + 1) * TN; t += WG) acc[t] = 0.0f;
+        for (int t = threadIdx.x; t < 4 * TN; t += WG) acc[t] = 0ull;
         __syncthreads();
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
-            const uvec<WM> w = load_record<WM>(words, s.W, cap, p);
-            double xd[DIM], vd[DIM], Cd[D2], Fd[D2];
-            dec_field<DIM, DIM>(s, 0, w, xd);
-            dec_field<DIM, DIM>(s, 1, w, vd);
-            dec_field<DIM, D2>(s, 2, w, Cd);
-            dec_field<DIM, D2>(s, 3, w, Fd);
+            double xd[DIM];
             float v[DIM], C[D2], F[D2];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) v[a] = (float)vd[a];
-#pragma unroll
-            for (int c = 0; c < D2; ++c) {
-                C[c] = (float)Cd[c];
-                F[c] = (float)Fd[c];
-            }
+            decode_all<DIM, float>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
             p2g_particle<DIM>(P, xd, v, C, F, origin, acc, gout, flags, fallback);
         }
         __syncthreads();
@@ -585,17 +627,20 @@ __global__ __launch_bounds__(WG) void k_p2g(DevScheme s, DevParams P, const uint
 }
 
 // ---------------------------------------------------------------------------
-// grid update: momentum -> velocity, gravity, walls; clears the other buffer
+// grid update: fixed-point sums -> velocity (mom/m + dt g, wall rule) in
+// place; clears the other buffer's touched blocks
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double from_fix(unsigned long long v) { return (double)(long long)v; }
+
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_grid_update(DevParams P, float4 *__restrict__ gcur,
-                                                    float4 *__restrict__ gnxt, uint32_t *__restrict__ fcur,
+__global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restrict__ gcur,
+                                                    GNode *__restrict__ gnxt, uint32_t *__restrict__ fcur,
                                                     uint32_t *__restrict__ fnxt, int64_t nblocks, uint64_t *stats) {
     constexpr int B = Geo<DIM>::BLK, CPB = Geo<DIM>::CPB, L = Geo<DIM>::LOG;
     const int64_t b = blockIdx.x;
     const bool tc = fcur[b] != 0u, tn = fnxt[b] != 0u;
     if (!tc && !tn) return;
-    int bc[3];
+    int bc[3] = {0, 0, 0};
     bc[0] = (int)(b % P.nb);
     if constexpr (DIM == 3) {
         bc[1] = (int)((b / P.nb) % P.nb);
@@ -607,76 +652,164 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, float4 *__restr
     for (int l = threadIdx.x; l < CPB; l += WG) {
         const int64_t idx = (b << (DIM * L)) + l;
         if (tc) {
-            float4 g = gcur[idx];
-            const float m = node_mass<DIM>(g);
+            const GNode g = gcur[idx];
+            const double m = from_fix(g.q[3]);
             float vel[3] = {0.0f, 0.0f, 0.0f};
-            if (m > 0.0f) {
+            if (m > 0.0) {
                 ++active;
-                const float mom[3] = {g.x, g.y, g.z};
                 int ijk[3];
                 ijk[0] = bc[0] * B + (l & (B - 1));
                 ijk[1] = bc[1] * B + ((l >> L) & (B - 1));
                 ijk[2] = (DIM == 3) ? bc[2] * B + (l >> (2 * L)) : 0;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
-                    float va = mom[a] / m + P.dt * P.g[a];
+                    float va = (float)(from_fix(g.q[a]) / m) + P.dt * P.g[a];
                     if (ijk[a] < P.bound && va < 0.0f) va = 0.0f;
                     if (ijk[a] >= P.res - P.bound && va > 0.0f) va = 0.0f;
                     vel[a] = va;
                 }
             }
-            if constexpr (DIM == 3) gcur[idx] = make_float4(vel[0], vel[1], vel[2], m > 0.0f ? m : 0.0f);
-            else gcur[idx] = make_float4(vel[0], vel[1], m > 0.0f ? m : 0.0f, 0.0f);
+            const float mass = m > 0.0 ? (float)(m * (1.0 / FIX_ONE)) * P.p_mass : 0.0f;
+            reinterpret_cast<float4 *>(gcur + idx)[0] = make_float4(vel[0], vel[1], vel[2], mass);
         }
-        if (tn) gnxt[idx] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (tn) {
+            ulonglong4 z;
+            z.x = z.y = z.z = z.w = 0ull;
+            reinterpret_cast<ulonglong4 *>(gnxt + idx)[0] = z;
+        }
     }
     if (tn && threadIdx.x == 0) fnxt[b] = 0u;
     add_stat(stats, ST_ACTIVE, active);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_clear_touched(float4 *__restrict__ g, uint32_t *__restrict__ flags,
+__global__ __launch_bounds__(WG) void k_clear_touched(GNode *__restrict__ g, uint32_t *__restrict__ flags,
                                                       int64_t nblocks) {
     constexpr int CPB = Geo<DIM>::CPB, L = Geo<DIM>::LOG;
     const int64_t b = blockIdx.x;
     if (flags[b] == 0u) return;
-    for (int l = threadIdx.x; l < CPB; l += WG) g[(b << (DIM * L)) + l] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int l = threadIdx.x; l < CPB; l += WG) {
+        ulonglong4 z;
+        z.x = z.y = z.z = z.w = 0ull;
+        reinterpret_cast<ulonglong4 *>(g + (b << (DIM * L)) + l)[0] = z;
+    }
     if (threadIdx.x == 0) flags[b] = 0u;
 }
 
 // ---------------------------------------------------------------------------
 // fused substep: G2P -> update -> dithered encode + store -> P2G (next step)
 // ---------------------------------------------------------------------------
+
+// G2P from the LDS tile, separable in the three axes:
+// v' = sum_i w v_i and S_b = sum_i w (o_b - f_b) v_i, C' = 4/dx S.
 template <int DIM>
-__device__ __forceinline__ void fetch_v(const float *__restrict__ gv, const float4 *__restrict__ gcur,
-                                        const DevParams &P, bool in_tile, int lidx, const int *ijk, float *vi) {
-    constexpr int TN = Geo<DIM>::TN;
-    if (in_tile) {
+__device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, const float (*wx)[3],
+                                         const float (*wd)[3], float *nv, float (*S)[DIM]) {
+    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN;
+    if constexpr (DIM == 3) {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) vi[a] = gv[a * TN + lidx];
+        for (int oz = 0; oz < 3; ++oz) {
+            float P00[3] = {0.f, 0.f, 0.f}, P01[3] = {0.f, 0.f, 0.f}, P10[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+                float R0[3] = {0.f, 0.f, 0.f}, R1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox) {
+                    const int idx = l0 + (oz * TB + oy) * TB + ox;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float vi = gv[a * TN + idx];
+                        R0[a] += wx[0][ox] * vi;
+                        R1[a] += wd[0][ox] * vi;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    P00[a] += wx[1][oy] * R0[a];
+                    P01[a] += wd[1][oy] * R0[a];
+                    P10[a] += wx[1][oy] * R1[a];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                nv[a] += wx[2][oz] * P00[a];
+                S[0][a] += wx[2][oz] * P10[a];
+                S[1][a] += wx[2][oz] * P01[a];
+                S[2][a] += wd[2][oz] * P00[a];
+            }
+        }
     } else {
-        const float4 g = gcur[node_index<DIM>(ijk, P.nb)];
-        vi[0] = g.x;
-        vi[1] = g.y;
-        if constexpr (DIM == 3) vi[DIM - 1] = g.z;
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            float R0[2] = {0.f, 0.f}, R1[2] = {0.f, 0.f};
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const int idx = l0 + oy * TB + ox;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float vi = gv[a * TN + idx];
+                    R0[a] += wx[0][ox] * vi;
+                    R1[a] += wd[0][ox] * vi;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                nv[a] += wx[1][oy] * R0[a];
+                S[0][a] += wx[1][oy] * R1[a];
+                S[1][a] += wd[1][oy] * R0[a];
+            }
+        }
     }
 }
 
-template <int DIM, int WM>
-__global__ __launch_bounds__(WG) void k_substep(DevScheme s, DevParams P, uint32_t *__restrict__ words,
+// G2P straight from the grid buffer, for a particle whose stencil left its tile.
+template <int DIM>
+__device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int nb, const int *base,
+                                                     const float (*wx)[3], const float (*wd)[3], float *nv,
+                                                     float (*S)[DIM]) {
+    constexpr int NST = Geo<DIM>::NST;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        int ijk[DIM];
+        float w = 1.0f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            w *= wx[a][o[a]];
+        }
+        const float4 g = reinterpret_cast<const float4 *>(gcur + node_index<DIM>(ijk, nb))[0];
+        const float vi[3] = {g.x, g.y, g.z};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            nv[a] += w * vi[a];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                float wdb = 1.0f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) wdb *= (c == b) ? wd[c][o[c]] : wx[c][o[c]];
+                S[b][a] += wdb * vi[a];
+            }
+        }
+    }
+}
+
+template <int DIM, bool RS>
+__global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__ sch, DevParams P, uint32_t *words,
                                                 int64_t cap, const WorkItem *__restrict__ items,
                                                 const uint32_t *__restrict__ n_items,
-                                                const float4 *__restrict__ gcur, float4 *__restrict__ gnxt,
+                                                const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
                                                 uint32_t *__restrict__ flags, uint32_t step, int do_p2g,
                                                 int collect_stats, uint64_t *stats) {
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
     __shared__ float gv[DIM * TN];
-    __shared__ float acc[(DIM + 1) * TN];
+    __shared__ unsigned long long acc[4 * TN];
     const uint32_t nit = *n_items;
     uint32_t fallback = 0;
     LaneStats ls;
     ls.clear();
-    for (uint32_t item = blockIdx.x; item < nit; item += gridDim.x) {
+    const ItemWalk walk(nit);
+    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
         const WorkItem it = items[item];
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
@@ -684,19 +817,22 @@ __global__ __launch_bounds__(WG) void k_substep(DevScheme s, DevParams P, uint32
         for (int t = threadIdx.x; t < TN; t += WG) {
             int ijk[DIM];
             float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (tile_node<DIM>(t, origin, P.res, ijk)) g = gcur[node_index<DIM>(ijk, P.nb)];
+            if (tile_node<DIM>(t, origin, P.res, ijk))
+                g = reinterpret_cast<const float4 *>(gcur + node_index<DIM>(ijk, P.nb))[0];
             gv[t] = g.x;
             gv[TN + t] = g.y;
             if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
         }
         if (do_p2g)
-            for (int t = threadIdx.x; t < (DIM + 1) * TN; t += WG) acc[t] = 0.0f;
+            for (int t = threadIdx.x; t < 4 * TN; t += WG) acc[t] = 0ull;
         __syncthreads();
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
-            uvec<WM> w = load_record<WM>(words, s.W, cap, p);
-            double xd[DIM], Fd[D2];
-            dec_field<DIM, DIM>(s, 0, w, xd);
-            dec_field<DIM, D2>(s, 3, w, Fd);
+            SchemeRef sp = scheme_ref(sch);
+            const uint32_t p4 = (uint32_t)p * 4u;
+            double xd[DIM];
+            float F[D2];
+            dec_field<DIM, 0, double>(&sp->f[0], words, cap, p4, xd);
+            dec_field<DIM, 3, float>(&sp->f[3], words, cap, p4, F);
             int base[DIM];
             float fx[DIM], wx[DIM][3], wd[DIM][3];
             stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
@@ -710,8 +846,6 @@ __global__ __launch_bounds__(WG) void k_substep(DevScheme s, DevParams P, uint32
                 l[a] = base[a] - origin[a];
                 in_tile &= (l[a] >= 0) && (l[a] <= TB - 3);
             }
-            if (!in_tile) fallback += 1;
-            // G2P: v' = sum w v_i, S_b = sum w (o_b - f_b) v_i, C' = 4/dx S
             float nv[DIM], S[DIM][DIM];  // S[b][a]
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -719,122 +853,42 @@ __global__ __launch_bounds__(WG) void k_substep(DevScheme s, DevParams P, uint32
 #pragma unroll
                 for (int b = 0; b < DIM; ++b) S[b][a] = 0.0f;
             }
-            if constexpr (DIM == 3) {
-                const int l0 = (l[2] * TB + l[1]) * TB + l[0];
-#pragma unroll
-                for (int oz = 0; oz < 3; ++oz) {
-                    float P00[DIM], P01[DIM], P10[DIM];
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) P00[a] = P01[a] = P10[a] = 0.0f;
-#pragma unroll
-                    for (int oy = 0; oy < 3; ++oy) {
-                        float R0[DIM], R1[DIM];
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) R0[a] = R1[a] = 0.0f;
-#pragma unroll
-                        for (int ox = 0; ox < 3; ++ox) {
-                            int ijk[DIM] = {base[0] + ox, base[1] + oy, base[DIM - 1] + oz};
-                            float vi[DIM];
-                            fetch_v<DIM>(gv, gcur, P, in_tile, l0 + (oz * TB + oy) * TB + ox, ijk, vi);
-#pragma unroll
-                            for (int a = 0; a < DIM; ++a) {
-                                R0[a] += wx[0][ox] * vi[a];
-                                R1[a] += wd[0][ox] * vi[a];
-                            }
-                        }
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            P00[a] += wx[1][oy] * R0[a];
-                            P01[a] += wd[1][oy] * R0[a];
-                            P10[a] += wx[1][oy] * R1[a];
-                        }
-                    }
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        nv[a] += wx[DIM - 1][oz] * P00[a];
-                        S[0][a] += wx[DIM - 1][oz] * P10[a];
-                        S[1][a] += wx[DIM - 1][oz] * P01[a];
-                        S[DIM - 1][a] += wd[DIM - 1][oz] * P00[a];
-                    }
-                }
+            if (in_tile) {
+                const int l0 = (DIM == 3) ? (l[DIM - 1] * TB + l[1]) * TB + l[0] : l[1] * TB + l[0];
+                g2p_tile<DIM>(gv, l0, wx, wd, nv, S);
             } else {
-                const int l0 = l[1] * TB + l[0];
-#pragma unroll
-                for (int oy = 0; oy < 3; ++oy) {
-                    float R0[DIM], R1[DIM];
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) R0[a] = R1[a] = 0.0f;
-#pragma unroll
-                    for (int ox = 0; ox < 3; ++ox) {
-                        int ijk[DIM] = {base[0] + ox, base[1] + oy};
-                        float vi[DIM];
-                        fetch_v<DIM>(gv, gcur, P, in_tile, l0 + oy * TB + ox, ijk, vi);
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            R0[a] += wx[0][ox] * vi[a];
-                            R1[a] += wd[0][ox] * vi[a];
-                        }
-                    }
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        nv[a] += wx[1][oy] * R0[a];
-                        S[0][a] += wx[1][oy] * R1[a];
-                        S[1][a] += wd[1][oy] * R0[a];
-                    }
-                }
+                fallback += 1;
+                g2p_global<DIM>(gcur, P.nb, base, wx, wd, nv, S);
             }
             // update: x' = x + dt v' (binary64), C' = 4/dx S, F' = (I + dt C') F
-            double xn[DIM], vn[DIM], Cn[D2], Fn[D2];
-            float Cf[D2];
+            double xn[DIM];
+            float Cn[D2], Fn[D2];
             {
 #pragma clang fp contract(off)
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    xn[a] = xd[a] + P.dt_d * (double)nv[a];
-                    vn[a] = (double)nv[a];
-                }
+                for (int a = 0; a < DIM; ++a) xn[a] = xd[a] + P.dt_d * (double)nv[a];
             }
 #pragma unroll
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
-                for (int b = 0; b < DIM; ++b) {
-                    Cf[a * DIM + b] = 4.0f * P.inv_dx * S[b][a];
-                    Cn[a * DIM + b] = (double)Cf[a * DIM + b];
-                }
+                for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] = 4.0f * P.inv_dx * S[b][a];
 #pragma unroll
             for (int i = 0; i < DIM; ++i)
 #pragma unroll
                 for (int j = 0; j < DIM; ++j) {
-                    float t = (float)Fd[i * DIM + j];
+                    float t = F[i * DIM + j];
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) t += P.dt * Cf[i * DIM + k] * (float)Fd[k * DIM + j];
-                    Fn[i * DIM + j] = (double)t;
+                    for (int k = 0; k < DIM; ++k) t += P.dt * Cn[i * DIM + k] * F[k * DIM + j];
+                    Fn[i * DIM + j] = t;
                 }
-            // dithered encode (Eq. 11) and in-place store
-            const uvec<16> rnd = dither_draws(s, (uint32_t)p, step, 1u);
-            uvec<WM> wo = 0;
-            enc_field<DIM, DIM>(s, 0, xn, rnd, wo, ls);
-            enc_field<DIM, DIM>(s, 1, vn, rnd, wo, ls);
-            enc_field<DIM, D2>(s, 2, Cn, rnd, wo, ls);
-            enc_field<DIM, D2>(s, 3, Fn, rnd, wo, ls);
-            store_record<WM>(words, s.W, cap, p, wo);
-            if (do_p2g) {
-                // P2G of the stored (quantized) state for the next substep (Eq. 1)
-                double qx[DIM], qv[DIM], qC[D2], qF[D2];
-                dec_field<DIM, DIM>(s, 0, wo, qx);
-                dec_field<DIM, DIM>(s, 1, wo, qv);
-                dec_field<DIM, D2>(s, 2, wo, qC);
-                dec_field<DIM, D2>(s, 3, wo, qF);
-                float v[DIM], C[D2], F[D2];
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) v[a] = (float)qv[a];
-#pragma unroll
-                for (int c = 0; c < D2; ++c) {
-                    C[c] = (float)qC[c];
-                    F[c] = (float)qF[c];
-                }
-                p2g_particle<DIM>(P, qx, v, C, F, origin, acc, gnxt, flags, fallback);
-            }
+            // dithered encode (Eq. 11), streamed in place in placement order
+            const Draws rnd = dither_draws(sp, (uint32_t)p, step, 1u);
+            OutStream os{words, cap, p4, 0ull, 0, 0};
+            double qx[DIM];
+            float qv[DIM], qC[D2], qF[D2];
+            encode_record<DIM, RS>(sch, xn, nv, Cn, Fn, rnd, os, ls, qx, qv, qC, qF);
+            // P2G of the stored (quantized) state for the next substep (Eq. 1)
+            if (do_p2g) p2g_particle<DIM>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
         }
         __syncthreads();
         if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags);
@@ -849,17 +903,22 @@ __global__ __launch_bounds__(WG) void k_substep(DevScheme s, DevParams P, uint32
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define MPMQ_DISPATCH(dim, wm, KERNEL, GRID, ...)                                                         \
-    do {                                                                                                   \
-        if ((dim) == 3 && (wm) == 16) hipLaunchKernelGGL((KERNEL<3, 16>), GRID, dim3(WG), 0, st, __VA_ARGS__); \
-        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, 32>), GRID, dim3(WG), 0, st, __VA_ARGS__);     \
-        else if ((wm) == 16) hipLaunchKernelGGL((KERNEL<2, 16>), GRID, dim3(WG), 0, st, __VA_ARGS__);     \
-        else hipLaunchKernelGGL((KERNEL<2, 32>), GRID, dim3(WG), 0, st, __VA_ARGS__);                      \
+#define MPMQ_DISPATCH(dim, wm, KERNEL, GRID, ...)                                                \
+    do {                                                                                          \
+        (void)(wm);                                                                               \
+        if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3>), GRID, dim3(WG), 0, st, __VA_ARGS__);      \
+        else hipLaunchKernelGGL((KERNEL<2>), GRID, dim3(WG), 0, st, __VA_ARGS__);                 \
+    } while (0)
+
+#define MPMQ_DISPATCH2(dim, KERNEL, FLAG, GRID, ...)                                                \
+    do {                                                                                            \
+        if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, FLAG>), GRID, dim3(WG), 0, st, __VA_ARGS__);  \
+        else hipLaunchKernelGGL((KERNEL<2, FLAG>), GRID, dim3(WG), 0, st, __VA_ARGS__);             \
     } while (0)
 
 static dim3 pgrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
 
-hipError_t launch_encode(int dim, int wm, const DevScheme &s, const float *x, const float *v, const float *C,
+hipError_t launch_encode(int dim, int wm, const DevScheme *s, const float *x, const float *v, const float *C,
                          const float *F, int64_t n, int64_t cap, uint32_t *words, uint32_t *ids, uint32_t step,
                          uint32_t tag, uint64_t *stats, hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -867,14 +926,14 @@ hipError_t launch_encode(int dim, int wm, const DevScheme &s, const float *x, co
     return hipGetLastError();
 }
 
-hipError_t launch_decode(int dim, int wm, const DevScheme &s, const uint32_t *words, int64_t n, int64_t cap,
+hipError_t launch_decode(int dim, int wm, const DevScheme *s, const uint32_t *words, int64_t n, int64_t cap,
                          float *x, float *v, float *C, float *F, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     MPMQ_DISPATCH(dim, wm, k_decode, pgrid(n), s, words, n, cap, x, v, C, F);
     return hipGetLastError();
 }
 
-hipError_t launch_sort_keys(int dim, int wm, const DevScheme &s, const DevParams &p, const uint32_t *words,
+hipError_t launch_sort_keys(int dim, int wm, const DevScheme *s, const DevParams &p, const uint32_t *words,
                             int64_t n, int64_t cap, uint32_t *keys, uint32_t *vals, uint32_t *cell_count,
                             hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -945,14 +1004,14 @@ hipError_t launch_items(const uint32_t *cell_start, const uint32_t *item_off, in
     return hipGetLastError();
 }
 
-hipError_t launch_p2g(int dim, int wm, const DevScheme &s, const DevParams &p, const uint32_t *words, int64_t cap,
-                      const WorkItem *items, const uint32_t *n_items, int grid, float4 *gout, uint32_t *flags_out,
+hipError_t launch_p2g(int dim, int wm, const DevScheme *s, const DevParams &p, const uint32_t *words, int64_t cap,
+                      const WorkItem *items, const uint32_t *n_items, int grid, GNode *gout, uint32_t *flags_out,
                       uint64_t *stats, hipStream_t st) {
     MPMQ_DISPATCH(dim, wm, k_p2g, dim3(grid), s, p, words, cap, items, n_items, gout, flags_out, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_grid_update(int dim, const DevParams &p, float4 *gcur, float4 *gnxt, uint32_t *flags_cur,
+hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *gnxt, uint32_t *flags_cur,
                               uint32_t *flags_nxt, int64_t nblocks, uint64_t *stats, hipStream_t st) {
     if (dim == 3)
         hipLaunchKernelGGL(k_grid_update<3>, dim3((unsigned)nblocks), dim3(WG), 0, st, p, gcur, gnxt, flags_cur,
@@ -963,7 +1022,7 @@ hipError_t launch_grid_update(int dim, const DevParams &p, float4 *gcur, float4 
     return hipGetLastError();
 }
 
-hipError_t launch_clear_touched(int dim, float4 *g, uint32_t *flags, int64_t nblocks, hipStream_t st) {
+hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblocks, hipStream_t st) {
     if (dim == 3)
         hipLaunchKernelGGL(k_clear_touched<3>, dim3((unsigned)nblocks), dim3(WG), 0, st, g, flags, nblocks);
     else
@@ -971,12 +1030,16 @@ hipError_t launch_clear_touched(int dim, float4 *g, uint32_t *flags, int64_t nbl
     return hipGetLastError();
 }
 
-hipError_t launch_substep(int dim, int wm, const DevScheme &s, const DevParams &p, uint32_t *words, int64_t cap,
-                          const WorkItem *items, const uint32_t *n_items, int grid, const float4 *gcur,
-                          float4 *gnxt, uint32_t *flags_nxt, uint32_t step, int do_p2g, int collect_stats,
-                          uint64_t *stats, hipStream_t st) {
-    MPMQ_DISPATCH(dim, wm, k_substep, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt, step,
-                  do_p2g, collect_stats, stats);
+hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &p, uint32_t *words, int64_t cap,
+                          const WorkItem *items, const uint32_t *n_items, int grid, const GNode *gcur,
+                          GNode *gnxt, uint32_t *flags_nxt, uint32_t step, int do_p2g, int collect_stats,
+                          int round_stats, uint64_t *stats, hipStream_t st) {
+    if (round_stats)
+        MPMQ_DISPATCH2(dim, k_substep, true, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
+                       step, do_p2g, collect_stats, stats);
+    else
+        MPMQ_DISPATCH2(dim, k_substep, false, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
+                       step, do_p2g, collect_stats, stats);
     return hipGetLastError();
 }
 

@@ -10,31 +10,86 @@ template <int N> using uvec = uint32_t __attribute__((ext_vector_type(N)));
 
 enum { K_FIXED = 0, K_SEXP = 1, K_RAW = 2 };
 
-// ---------------------------------------------------------------------------
-// Bit pack (Sec. 7, Figs. 7-8).  A record of W words lives in a register
-// vector; a component is located by a wave-uniform descriptor, so the
-// indexed register reads compile to uniform indexed moves (no scratch).  A
-// component that spans two words is rebuilt with one funnel shift: alignbit
-// concatenates (hi:lo) and shifts right, the mask keeps `bits` bits.
-// ---------------------------------------------------------------------------
-template <int WM>
-__device__ __forceinline__ uint32_t get_code(const uvec<WM> &w, uint32_t desc, uint32_t mask) {
-    const uint32_t k = desc & 0xffu, kh = (desc >> 8) & 0xffu, sh = (desc >> 16) & 0xffu;
-    return __builtin_amdgcn_alignbit(w[kh], w[k], sh) & mask;
+// Makes a value opaque to the optimizer at this point, so that quantities
+// derived from it are recomputed here instead of being hoisted out of the
+// particle loop and kept live (the scheme constants and per-component row
+// addresses would otherwise exhaust the scalar registers).
+template <typename P> __device__ __forceinline__ P opaque(P v) {
+    asm volatile("" : "+s"(v));
+    return v;
 }
 
-template <int WM>
-__device__ __forceinline__ void put_code(uvec<WM> &w, uint32_t desc, uint32_t code) {
-    const uint32_t k = desc & 0xffu, sh = (desc >> 16) & 0xffu;
-    w[k] |= code << sh;
-    if (desc >> 24) w[k + 1] |= code >> (32u - sh);  // spans => sh > 0
+// The scheme lives in device memory that no kernel writes; reading it
+// through the constant address space keeps every field in scalar registers.
+typedef const __attribute__((address_space(4))) DevScheme *SchemeRef;
+__device__ __forceinline__ SchemeRef scheme_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
+typedef const __attribute__((address_space(4))) DevField *FieldRef;
+
+
+// ---------------------------------------------------------------------------
+// Canonical component numbering x, v, C, F (matrices row-major); it fixes
+// the Philox draw of every component independently of the placement order.
+// ---------------------------------------------------------------------------
+template <int DIM, int FID> constexpr int ncomp() { return FID < 2 ? DIM : DIM * DIM; }
+template <int DIM, int FID> constexpr int canon0() {
+    return FID == 0 ? 0 : FID == 1 ? DIM : FID == 2 ? 2 * DIM : 2 * DIM + DIM * DIM;
 }
+
+// ---------------------------------------------------------------------------
+// Bit pack (Sec. 7, Figs. 7-8), word-major: word k of slot p is
+// words[k * cap + p].  A component at record bit o is read from word o/32
+// (and o/32 + 1 when it spans two words) at a wave-uniform row offset and a
+// per-lane byte offset p4 = 4p, then rebuilt with one funnel shift:
+// alignbit concatenates (hi:lo) and shifts right, the mask keeps `bits` bits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ld_row(const uint32_t *words, int64_t cap, int k, uint32_t p4) {
+    const char *row = reinterpret_cast<const char *>(words + (int64_t)k * cap);
+    return *reinterpret_cast<const uint32_t *>(row + p4);
+}
+
+__device__ __forceinline__ uint32_t get_comp(const uint32_t *words, int64_t cap, uint32_t p4, int o, int bits,
+                                             uint32_t mask) {
+    const int k = o >> 5, sh = o & 31;
+    const uint32_t lo = ld_row(words, cap, k, p4);
+    uint32_t hi = 0u;
+    if (sh + bits > 32) hi = ld_row(words, cap, k + 1, p4);
+    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)sh) & mask;
+}
+
+// Encoder output: codes arrive in placement order and are appended to a
+// 64-bit accumulator; each completed word is stored at once (the fill level
+// is wave-uniform, so the test is a scalar branch and no record is ever
+// indexed in registers).
+struct OutStream {
+    uint32_t *words;
+    int64_t cap;
+    uint32_t p4;
+    uint64_t acc;
+    int nb, k;
+    __device__ __forceinline__ void emit(uint32_t code, int bits) {
+        acc |= (uint64_t)code << nb;
+        nb += bits;
+        if (nb >= 32) {
+            char *row = reinterpret_cast<char *>(words + (int64_t)k * cap);
+            __builtin_nontemporal_store((uint32_t)acc, reinterpret_cast<uint32_t *>(row + p4));
+            acc >>= 32;
+            nb -= 32;
+            ++k;
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        if (nb > 0) {
+            char *row = reinterpret_cast<char *>(words + (int64_t)k * cap);
+            __builtin_nontemporal_store((uint32_t)acc, reinterpret_cast<uint32_t *>(row + p4));
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies with the published multipliers, key bumped by the
 // Weyl constants between rounds.  Counter (slot, step, group, tag), key =
-// seed.  Record component k takes 16 bits: half k%2 of word k/2 of the
+// seed.  Canonical component k takes 16 bits: half k%2 of word k/2 of the
 // concatenated group outputs.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -55,33 +110,34 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-__device__ __forceinline__ uvec<16> dither_draws(const DevScheme &s, uint32_t slot, uint32_t step,
-                                                 uint32_t tag) {
-    uvec<16> r = 0;
+struct Draws {
+    uint32_t r[12];
+};
+
+__device__ __forceinline__ Draws dither_draws(SchemeRef s, uint32_t slot, uint32_t step, uint32_t tag) {
+    Draws d;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if ((s.dither_groups >> j) & 1u) {
-            uint32_t o[4];
-            philox10(slot, step, (uint32_t)j, tag, s.seed_lo, s.seed_hi, o);
-            r[4 * j + 0] = o[0];
-            r[4 * j + 1] = o[1];
-            r[4 * j + 2] = o[2];
-            r[4 * j + 3] = o[3];
+    for (int j = 0; j < 3; ++j) {
+        if ((s->dither_groups >> j) & 1u) {
+            philox10(slot, step, (uint32_t)j, tag, s->seed_lo, s->seed_hi, &d.r[4 * j]);
+        } else {
+            d.r[4 * j] = d.r[4 * j + 1] = d.r[4 * j + 2] = d.r[4 * j + 3] = 0u;
         }
     }
-    return r;
+    return d;
 }
 
-// xi' in (0,1): (r16 + 1/2) 2^-16, exact in binary64.
-__device__ __forceinline__ double dither_xi(const uvec<16> &r, int k) {
-    const uint32_t w = r[k >> 1];
+// xi' in (0,1): (r16 + 1/2) 2^-16, exact in binary64; k is a compile-time index.
+__device__ __forceinline__ double dither_xi(const Draws &d, int k) {
+    const uint32_t w = d.r[k >> 1];
     const uint32_t h = (k & 1) ? (w >> 16) : (w & 0xffffu);
     return ((double)h + 0.5) * (1.0 / 65536.0);
 }
 
 // ---------------------------------------------------------------------------
 // Encoder statistics kept per lane and flushed per work item:
-// ud[f] = round-ups | round-downs << 16, sat / nan: 8 bits per field.
+// ud[f] = round-ups | round-downs << 16 (counted only when the RS template
+// flag is set), sat / nan: 8 bits per field.
 // ---------------------------------------------------------------------------
 struct LaneStats {
     uint32_t ud[4];
@@ -92,10 +148,11 @@ struct LaneStats {
 // Fixed point (Eq. 3, Eq. 11 when r = xi): binary64, no contraction, so the
 // rounding sequence is exactly t = RN(RN(val - lo) * inv), s = RN(t + r),
 // u = clamp(floor(s)).
-__device__ __forceinline__ uint32_t enc_fixed(const DevField &f, double val, double r, int fid,
+template <bool RS>
+__device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, double r, int fid,
                                               LaneStats &ls) {
 #pragma clang fp contract(off)
-    const double t = (val - f.lo) * f.inv;
+    const double t = (val - f->lo) * f->inv;
     const double sv = t + r;
     const double fl = floor(sv);
     uint32_t code;
@@ -105,142 +162,155 @@ __device__ __forceinline__ uint32_t enc_fixed(const DevField &f, double val, dou
     } else if (fl < 0.0) {
         code = 0u;
         ls.sat += 1u << (8 * fid);
-    } else if (fl > f.maxc) {
-        code = (uint32_t)f.maxc;
+    } else if (fl > f->maxc) {
+        code = (uint32_t)f->maxc;
         ls.sat += 1u << (8 * fid);
     } else {
         code = (uint32_t)fl;
-        ls.ud[fid] += (fl > floor(t)) ? 1u : 0x10000u;
+        if (RS) ls.ud[fid] += (fl > floor(t)) ? 1u : 0x10000u;
     }
     return code;
 }
 
 // Shared-exponent vector: E from the largest magnitude, raised by one if a
-// magnitude rounds up to 2^(m-1); then sign | magnitude per component.
-template <int NC, int WM>
-__device__ __forceinline__ void enc_sexp(const DevScheme &s, int fid, const double *val,
-                                         const uvec<16> &rnd, uvec<WM> &w, LaneStats &ls) {
+// magnitude rounds up to 2^(m-1); stored as E - E_min, then sign|magnitude.
+template <int DIM, int FID, typename T, bool RS>
+__device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, const Draws &rnd, OutStream &os,
+                                         LaneStats &ls, T *qv) {
 #pragma clang fp contract(off)
-    const DevField &f = s.f[fid];
-    const int m1 = f.bits - 1;
-    const double qmax = (double)f.mag_mask;
-    double a[NC];
+    constexpr int NC = ncomp<DIM, FID>(), K0 = canon0<DIM, FID>();
+    const int m1 = f->bits - 1;
+    const double qmax = (double)f->mag_mask;
     double M = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double x = val[c];
-        if (!(x == x)) {
-            ls.nan += 1u << (8 * fid);
-            x = 0.0;
-        }
-        a[c] = fabs(x);
-        M = fmax(M, a[c]);
+        const double x = (double)val[c];
+        if (!(x == x)) ls.nan += 1u << (8 * FID);
+        else M = fmax(M, fabs(x));
     }
     int E;
-    if (M == 0.0) E = f.emin;
-    else if (isinf(M)) E = f.emax;
-    else E = min(max(ilogb(M) + 1, f.emin), f.emax);
-    double q[NC], t[NC];
-    bool over = true;
-    while (over) {
-        over = false;
+    if (M == 0.0) E = f->emin;
+    else if (isinf(M)) E = f->emax;
+    else E = min(max(ilogb(M) + 1, f->emin), f->emax);
+    // raise E while a magnitude rounds up to 2^(m-1) (at most once in exact
+    // arithmetic; the loop keeps the definition literal)
+    for (;;) {
+        bool over = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            t[c] = ldexp(a[c], m1 - E);
-            const double r = f.dither ? dither_xi(rnd, f.k0 + c) : 0.5;
-            q[c] = floor(t[c] + r);
-            over |= q[c] > qmax;
+            double x = (double)val[c];
+            x = (x == x) ? fabs(x) : 0.0;
+            const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
+            over |= floor(ldexp(x, m1 - E) + r) > qmax;
         }
-        if (over && E < f.emax) E += 1;
-        else over = false;
+        if (!(over && E < f->emax)) break;
+        E += 1;
     }
-    put_code(w, f.exp_desc, (uint32_t)(E - f.emin));
+    os.emit((uint32_t)(E - f->emin), f->exp_bits);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+        double x = (double)val[c];
+        x = (x == x) ? fabs(x) : 0.0;
+        const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
+        const double t = ldexp(x, m1 - E);
+        const double q = floor(t + r);
         uint32_t qc;
-        if (q[c] > qmax) {
-            qc = f.mag_mask;
-            ls.sat += 1u << (8 * fid);
+        if (q > qmax) {
+            qc = f->mag_mask;
+            ls.sat += 1u << (8 * FID);
         } else {
-            qc = (uint32_t)q[c];
-            ls.ud[fid] += (q[c] > floor(t[c])) ? 1u : 0x10000u;
+            qc = (uint32_t)q;
+            if (RS) ls.ud[FID] += (q > floor(t)) ? 1u : 0x10000u;
         }
-        const uint32_t sign = (val[c] < 0.0 && qc > 0u) ? 1u : 0u;
-        put_code(w, s.cdesc[fid][c], qc | (sign << m1));
+        const bool neg = (double)val[c] < 0.0 && qc > 0u;
+        os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);
+        const double mag = ldexp((double)qc, E - m1);
+        qv[c] = (T)(neg ? -mag : mag);
     }
 }
 
-// Encode NC values of field `fid` into the record (values are the full
-// attribute; the identity is removed here for a REL_IDENTITY field).
-template <int DIM, int NC, int WM>
-__device__ __forceinline__ void enc_field(const DevScheme &s, int fid, const double *val,
-                                          const uvec<16> &rnd, uvec<WM> &w, LaneStats &ls) {
+// Encodes field FID (values are the full attribute; the identity is removed
+// here for a REL_IDENTITY field), appends its codes to the stream and
+// returns the decoded stored values in qv (Eq. 1: the next substep starts
+// from these).  T is double for x and float for v, C, F.
+template <int DIM, int FID, typename T, bool RS>
+__device__ __forceinline__ void enc_field(const FieldRef f, const T *val, const Draws &rnd, OutStream &os,
+                                          LaneStats &ls, T *qv) {
 #pragma clang fp contract(off)
-    const DevField &f = s.f[fid];
-    double rel[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) rel[c] = (f.rel && (c % (DIM + 1) == 0)) ? val[c] - 1.0 : val[c];
-    if (f.kind == K_FIXED) {
+    constexpr int NC = ncomp<DIM, FID>(), K0 = canon0<DIM, FID>();
+    if (f->kind == K_FIXED) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double r = f.dither ? dither_xi(rnd, f.k0 + c) : 0.5;
-            put_code(w, s.cdesc[fid][c], enc_fixed(f, rel[c], r, fid, ls));
+            const bool diag = f->rel && (c % (DIM + 1) == 0);
+            const double rel = diag ? (double)val[c] - 1.0 : (double)val[c];
+            const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
+            const uint32_t code = enc_fixed<RS>(f, rel, r, FID, ls);
+            os.emit(code, f->bits);
+            const double q = fma((double)code, f->delta, f->lo);
+            qv[c] = (T)(diag ? q + 1.0 : q);
         }
-    } else if (f.kind == K_RAW) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) put_code(w, s.cdesc[fid][c], __float_as_uint((float)rel[c]));
-    } else {
-        enc_sexp<NC>(s, fid, rel, rnd, w, ls);
-    }
-}
-
-// Decode field `fid` exactly in binary64 (the identity added back for a
-// REL_IDENTITY field).
-template <int DIM, int NC, int WM>
-__device__ __forceinline__ void dec_field(const DevScheme &s, int fid, const uvec<WM> &w, double *out) {
-#pragma clang fp contract(off)
-    const DevField &f = s.f[fid];
-    if (f.kind == K_FIXED) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            out[c] = fma((double)get_code(w, s.cdesc[fid][c], s.cmask[fid][c]), f.delta, f.lo);
-    } else if (f.kind == K_RAW) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            out[c] = (double)__uint_as_float(get_code(w, s.cdesc[fid][c], s.cmask[fid][c]));
-    } else {
-        const int E = (int)get_code(w, f.exp_desc, f.exp_mask) + f.emin;
-        const int m1 = f.bits - 1;
+    } else if (f->kind == K_RAW) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const uint32_t q = get_code(w, s.cdesc[fid][c], s.cmask[fid][c]);
-            const double mag = ldexp((double)(q & f.mag_mask), E - m1);
-            out[c] = ((q >> m1) & 1u) ? -mag : mag;
+            const bool diag = f->rel && (c % (DIM + 1) == 0);
+            const float fv = (float)(diag ? (double)val[c] - 1.0 : (double)val[c]);
+            os.emit(__float_as_uint(fv), 32);
+            qv[c] = (T)(diag ? (double)fv + 1.0 : (double)fv);
+        }
+    } else {
+        enc_sexp<DIM, FID, T, RS>(f, val, rnd, os, ls, qv);  // REL_IDENTITY is rejected for this kind
+    }
+}
+
+// Decodes field FID exactly in binary64 (identity added back for a
+// REL_IDENTITY field) and rounds once to T.
+template <int DIM, int FID, typename T>
+__device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *words, int64_t cap, uint32_t p4,
+                                          T *out) {
+#pragma clang fp contract(off)
+    constexpr int NC = ncomp<DIM, FID>();
+    if (f->kind == K_FIXED) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double q = fma((double)get_comp(words, cap, p4, f->off + c * f->bits, f->bits, f->mask), f->delta, f->lo);
+            out[c] = (T)((f->rel && (c % (DIM + 1) == 0)) ? q + 1.0 : q);
+        }
+    } else if (f->kind == K_RAW) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double q = (double)__uint_as_float(get_comp(words, cap, p4, f->off + 32 * c, 32, 0xffffffffu));
+            out[c] = (T)((f->rel && (c % (DIM + 1) == 0)) ? q + 1.0 : q);
+        }
+    } else {
+        const int E = (int)get_comp(words, cap, p4, f->off, f->exp_bits, f->exp_mask) + f->emin;
+        const int m1 = f->bits - 1;
+        const int o0 = f->off + f->exp_bits;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const uint32_t q = get_comp(words, cap, p4, o0 + c * f->bits, f->bits, f->mask);
+            const double mag = ldexp((double)(q & f->mag_mask), E - m1);
+            out[c] = (T)(((q >> m1) & 1u) ? -mag : mag);
         }
     }
-    if (f.rel) {
-#pragma unroll
-        for (int c = 0; c < NC; c += DIM + 1) out[c] = out[c] + 1.0;
+}
+
+
+
+// Encodes all four fields in placement order; qx.. receive the stored values.
+template <int DIM, bool RS>
+__device__ __forceinline__ void encode_record(const DevScheme *sp, const double *x, const float *v,
+                                              const float *C, const float *F, const Draws &rnd, OutStream &os,
+                                              LaneStats &ls, double *qx, float *qv, float *qC, float *qF) {
+#pragma unroll 1
+    for (int slot = 0; slot < 4; ++slot) {
+        SchemeRef s = scheme_ref(sp);
+        const int fid = s->order[slot];
+        if (fid == 0) enc_field<DIM, 0, double, RS>(&s->f[0], x, rnd, os, ls, qx);
+        else if (fid == 1) enc_field<DIM, 1, float, RS>(&s->f[1], v, rnd, os, ls, qv);
+        else if (fid == 2) enc_field<DIM, 2, float, RS>(&s->f[2], C, rnd, os, ls, qC);
+        else enc_field<DIM, 3, float, RS>(&s->f[3], F, rnd, os, ls, qF);
     }
-}
-
-// Loads the W words of slot p (word-major, stride cap) into a register record.
-template <int WM>
-__device__ __forceinline__ uvec<WM> load_record(const uint32_t *__restrict__ words, int W, int64_t cap,
-                                                int64_t p) {
-    uvec<WM> w = 0;
-#pragma unroll
-    for (int k = 0; k < WM; ++k)
-        if (k < W) w[k] = __builtin_nontemporal_load(words + (int64_t)k * cap + p);
-    return w;
-}
-
-template <int WM>
-__device__ __forceinline__ void store_record(uint32_t *__restrict__ words, int W, int64_t cap, int64_t p,
-                                             const uvec<WM> &w) {
-#pragma unroll
-    for (int k = 0; k < WM; ++k)
-        if (k < W) __builtin_nontemporal_store(w[k], words + (int64_t)k * cap + p);
+    os.finish();
 }
 
 // ---------------------------------------------------------------------------

@@ -25,27 +25,35 @@ constexpr int MAX_WORDS = 32;    // record <= 1024 bits
 // One field's codec constants (indexed by field id x=0, v=1, C=2, F=3).
 struct DevField {
     int32_t kind, bits, exp_bits, dither;
-    int32_t rel, ncomp, k0, pad0;        // k0: first Philox component index
-    int32_t emin, emax;                  // SHARED_EXP exponent range
-    uint32_t exp_desc, exp_mask;         // SHARED_EXP exponent location
-    uint32_t mag_mask, pad1;             // SHARED_EXP magnitude mask (bits-1 ones)
+    int32_t rel, off, emin, emax;        // off: first record bit (SHARED_EXP: exponent)
+    uint32_t mask, exp_mask, mag_mask, pad0;
     double lo, delta, inv, maxc;         // FIXED: range start, step, 2^b/(hi-lo), 2^b-1
 };
 
-// Component location word | hiword<<8 | shift<<16 | spans<<24.
 struct DevScheme {
     int32_t dim, W;
     uint32_t seed_lo, seed_hi;
-    uint32_t dither_groups;              // bit j: Philox group j is needed
+    uint32_t dither_groups;              // bit j: Philox group j (canonical comps 8j..8j+7) is needed
+    int32_t order[4];                    // placement order of the field ids
     int32_t pad[3];
     DevField f[4];
-    uint32_t cdesc[4][9];
-    uint32_t cmask[4][9];
 };
+
+// Grid node.  During P2G: exact fixed-point sums (two's complement int64,
+// 2^-32 resolution) of momentum and mass per unit particle mass; integer
+// addition is associative, so the sums do not depend on the order of the
+// atomics.  After the grid update the first 16 bytes hold the float
+// velocity and mass (float4).
+struct alignas(32) GNode {
+    unsigned long long q[4];
+};
+constexpr double FIX_ONE = 4294967296.0;          // 2^32
+constexpr double FIX_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+constexpr unsigned long long FIX_MAGIC_BITS = 0x4338000000000000ull;
 
 struct DevParams {
     int32_t dim, res, bound, nb;         // nb: node blocks per axis
-    float dt, inv_dx, dx, mu, la, p_mass, stress_coef, pad;
+    float dt, inv_dx, dx, mu, la, p_mass, stress_over_m, pad;
     float g[3], pad2;
     double dt_d, inv_dx_d;
 };
@@ -67,6 +75,7 @@ struct Scratch {
     int64_t flags;                       // 2 * nblocks uint32 touched flags
     int64_t stats;                       // ST_COUNT uint64
     int64_t misc;                        // 64 uint32 (n_items, ...)
+    int64_t scheme;                      // device copy of the DevScheme
     int64_t total;
     int64_t ncells, nblocks, max_items, hist_entries, scan_tmp_entries;
 };
@@ -78,12 +87,12 @@ struct Launch {
     hipStream_t stream;
 };
 
-hipError_t launch_encode(int dim, int wm, const DevScheme &s, const float *x, const float *v,
+hipError_t launch_encode(int dim, int wm, const DevScheme *s, const float *x, const float *v,
                          const float *C, const float *F, int64_t n, int64_t cap, uint32_t *words,
                          uint32_t *ids, uint32_t step, uint32_t tag, uint64_t *stats, hipStream_t st);
-hipError_t launch_decode(int dim, int wm, const DevScheme &s, const uint32_t *words, int64_t n,
+hipError_t launch_decode(int dim, int wm, const DevScheme *s, const uint32_t *words, int64_t n,
                          int64_t cap, float *x, float *v, float *C, float *F, hipStream_t st);
-hipError_t launch_sort_keys(int dim, int wm, const DevScheme &s, const DevParams &p,
+hipError_t launch_sort_keys(int dim, int wm, const DevScheme *s, const DevParams &p,
                             const uint32_t *words, int64_t n, int64_t cap, uint32_t *keys,
                             uint32_t *vals, uint32_t *cell_count, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t n, hipStream_t st);
@@ -99,16 +108,16 @@ hipError_t launch_items(const uint32_t *cell_start, const uint32_t *block_items_
 hipError_t launch_gather_u32(const uint32_t *in, const uint32_t *perm, uint32_t *out, int64_t n,
                              hipStream_t st);
 hipError_t launch_copy_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
-hipError_t launch_p2g(int dim, int wm, const DevScheme &s, const DevParams &p, const uint32_t *words,
+hipError_t launch_p2g(int dim, int wm, const DevScheme *s, const DevParams &p, const uint32_t *words,
                       int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
-                      float4 *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st);
-hipError_t launch_grid_update(int dim, const DevParams &p, float4 *gcur, float4 *gnxt,
+                      GNode *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st);
+hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *gnxt,
                               uint32_t *flags_cur, uint32_t *flags_nxt, int64_t nblocks,
                               uint64_t *stats, hipStream_t st);
-hipError_t launch_clear_touched(int dim, float4 *g, uint32_t *flags, int64_t nblocks, hipStream_t st);
-hipError_t launch_substep(int dim, int wm, const DevScheme &s, const DevParams &p, uint32_t *words,
+hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblocks, hipStream_t st);
+hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &p, uint32_t *words,
                           int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
-                          const float4 *gcur, float4 *gnxt, uint32_t *flags_nxt, uint32_t step,
-                          int do_p2g, int collect_stats, uint64_t *stats, hipStream_t st);
+                          const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, uint32_t step,
+                          int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st);
 
 }  // namespace mpmq

@@ -39,14 +39,16 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
     ds.seed_lo = (uint32_t)sc->seed;
     ds.seed_hi = (uint32_t)(sc->seed >> 32);
     bool seen[4] = {false, false, false, false};
-    int off = 0, k = 0;
+    int off = 0;
     static const char *names[4] = {"x", "v", "C", "F"};
+    const int dim = sc->dim;
     for (int i = 0; i < 4; ++i) {
         const mpmq_field_scheme &f = sc->fields[i];
         if (f.field < 0 || f.field > 3 || seen[f.field]) { err = "fields must be x, v, C, F each exactly once"; return false; }
         seen[f.field] = true;
+        ds.order[i] = f.field;
         const char *nm = names[f.field];
-        const int nc = ncomp(f.field, sc->dim);
+        const int nc = ncomp(f.field, dim);
         const bool rel = (f.flags & MPMQ_REL_IDENTITY) != 0;
         if (rel && f.field != MPMQ_FIELD_F) { err = std::string("REL_IDENTITY is only valid for F (field ") + nm + ")"; return false; }
         DevField &d = ds.f[f.field];
@@ -55,8 +57,8 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
         d.exp_bits = f.exp_bits;
         d.dither = f.dither ? 1 : 0;
         d.rel = rel ? 1 : 0;
-        d.ncomp = nc;
-        d.k0 = k;
+        d.off = off;
+        d.mask = (f.bits >= 32) ? 0xffffffffu : (uint32_t)((1ull << f.bits) - 1ull);
         if (f.kind == MPMQ_FIXED) {
             if (f.bits < 1 || f.bits > 32) { err = std::string("field ") + nm + ": FIXED bits must be in [1, 32]"; return false; }
             if (!(f.hi > f.lo) || !std::isfinite(f.lo) || !std::isfinite(f.hi)) { err = std::string("field ") + nm + ": need finite lo < hi"; return false; }
@@ -71,10 +73,6 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
             d.emax = ceil_log2_double(f.hi);
             d.emin = d.emax - ((1 << f.exp_bits) - 1);
             d.mag_mask = (uint32_t)((1ull << (f.bits - 1)) - 1ull);
-            const int sh = off & 31;
-            const int span = (sh + f.exp_bits > 32) ? 1 : 0;
-            d.exp_desc = (uint32_t)(off >> 5) | ((uint32_t)((off >> 5) + span) << 8) | ((uint32_t)sh << 16) |
-                         ((uint32_t)span << 24);
             d.exp_mask = (uint32_t)((1ull << f.exp_bits) - 1ull);
             off += f.exp_bits;
         } else if (f.kind == MPMQ_RAW_F32) {
@@ -83,17 +81,11 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
             err = std::string("field ") + nm + ": unknown kind";
             return false;
         }
-        for (int c = 0; c < nc; ++c) {
-            const int sh = off & 31;
-            const int span = (sh + f.bits > 32) ? 1 : 0;
-            ds.cdesc[f.field][c] = (uint32_t)(off >> 5) | ((uint32_t)((off >> 5) + span) << 8) |
-                                   ((uint32_t)sh << 16) | ((uint32_t)span << 24);
-            ds.cmask[f.field][c] = (f.bits == 32) ? 0xffffffffu : (uint32_t)((1ull << f.bits) - 1ull);
-            off += f.bits;
-        }
+        off += nc * f.bits;
+        // canonical component numbering x, v, C, F selects the Philox groups
+        const int k0 = f.field == 0 ? 0 : f.field == 1 ? dim : f.field == 2 ? 2 * dim : 2 * dim + dim * dim;
         if (d.dither && f.kind != MPMQ_RAW_F32)
-            for (int c = 0; c < nc; ++c) ds.dither_groups |= 1u << ((k + c) / 8);
-        k += nc;
+            for (int c = 0; c < nc; ++c) ds.dither_groups |= 1u << ((k0 + c) / 8);
     }
     if (off > 32 * MAX_WORDS) { err = "record longer than 1024 bits"; return false; }
     total_bits = off;
@@ -125,7 +117,7 @@ bool compile_params(const mpmq_params *pp, int dim, DevParams &dp, std::string &
     dp.mu = (float)mu;
     dp.la = (float)la;
     dp.p_mass = (float)(pp->rho * pp->p_vol);
-    dp.stress_coef = (float)(-pp->dt * pp->p_vol * 4.0 * inv_dx * inv_dx);
+    dp.stress_over_m = (float)(-pp->dt * 4.0 * inv_dx * inv_dx / pp->rho);
     for (int a = 0; a < 3; ++a) dp.g[a] = (float)pp->gravity[a];
     dp.dt_d = pp->dt;
     dp.inv_dx_d = inv_dx;
@@ -165,6 +157,7 @@ Scratch plan_scratch(int dim, int res, int64_t cap_pad) {
     s.flags = o; o = align256(o + 4 * 2 * s.nblocks);
     s.stats = o; o = align256(o + 8 * ST_COUNT);
     s.misc = o; o = align256(o + 256);
+    s.scheme = o; o = align256(o + (int64_t)sizeof(DevScheme));
     s.total = o;
     return s;
 }
@@ -179,7 +172,7 @@ struct mpmq_ctx {
     int64_t cap = 0, cap_pad = 0;
     hipStream_t stream = nullptr;
     uint32_t *words = nullptr;
-    float4 *grid[2] = {nullptr, nullptr};
+    GNode *grid[2] = {nullptr, nullptr};
     uint32_t *ids = nullptr;
     char *scratch = nullptr;
     Scratch sp;
@@ -187,6 +180,7 @@ struct mpmq_ctx {
     bool encoded = false, sorted = false, p2g_ready = false;
     int item_cap = 256, launch_grid = 1;
     bool timing = false;
+    int stats_level = 0;
     std::vector<EventPair> events;
     std::map<std::string, std::pair<int64_t, double>> times;
     std::string err;
@@ -196,6 +190,7 @@ struct mpmq_ctx {
     uint32_t *flags(int i) { return u32(sp.flags) + (int64_t)i * sp.nblocks; }
     uint32_t *n_items() { return u32(sp.misc); }
     WorkItem *items() { return reinterpret_cast<WorkItem *>(scratch + sp.items); }
+    const DevScheme *dscheme() { return reinterpret_cast<const DevScheme *>(scratch + sp.scheme); }
 };
 
 namespace {
@@ -245,10 +240,11 @@ mpmq_status do_sort(mpmq_ctx *c) {
     while (cap < 4096 && (int64_t)cap * 2 * 2048 <= n) cap *= 2;
     c->item_cap = cap;
     const int64_t upper = std::min<int64_t>(s.nblocks, n) + (n + cap - 1) / cap + 1;
-    c->launch_grid = (int)std::max<int64_t>(1, std::min<int64_t>(upper, 4096));
+    // persistent grid, a multiple of the 8 XCDs (see ItemWalk)
+    c->launch_grid = (int)std::max<int64_t>(8, ((std::min<int64_t>(upper, 4096) + 7) / 8) * 8);
     Timed t(c, "sort");
     HIPCHK(c, launch_fill_u32(cells, 0u, s.ncells + 1, st), "sort: clear cells");
-    HIPCHK(c, launch_sort_keys(c->dim, c->wm, c->ds, c->dp, c->words, n, c->cap_pad, c->u32(s.keys),
+    HIPCHK(c, launch_sort_keys(c->dim, c->wm, c->dscheme(), c->dp, c->words, n, c->cap_pad, c->u32(s.keys),
                                c->u32(s.vals), cells, st), "sort: keys");
     int kbits = 1;
     while (((int64_t)1 << kbits) < s.ncells) ++kbits;
@@ -306,7 +302,7 @@ mpmq_status mpmq_query_sizes(const mpmq_scheme *scheme, const mpmq_params *param
     std::string err;
     if (!compile_scheme(scheme, ds, bits, err)) return fail(nullptr, MPMQ_EINVAL, err);
     if (!compile_params(params, ds.dim, dp, err)) return fail(nullptr, MPMQ_EINVAL, err);
-    if (capacity < 1 || capacity > (int64_t)0x7fffff00) return fail(nullptr, MPMQ_ENOMEM, "capacity must be in [1, 2^31-256]");
+    if (capacity < 1 || capacity > (int64_t)0x3fffff00) return fail(nullptr, MPMQ_ENOMEM, "capacity must be in [1, 2^30-256]");
     const int64_t cap_pad = (capacity + 255) & ~(int64_t)255;
     const Scratch sp = plan_scratch(ds.dim, dp.res, cap_pad);
     const int CPB = ds.dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
@@ -314,7 +310,7 @@ mpmq_status mpmq_query_sizes(const mpmq_scheme *scheme, const mpmq_params *param
     out->record_bits = bits;
     out->capacity_padded = cap_pad;
     out->packed_bytes = 4 * (int64_t)ds.W * cap_pad;
-    out->grid_bytes = 16 * sp.nblocks * CPB;
+    out->grid_bytes = (int64_t)sizeof(GNode) * sp.nblocks * CPB;
     out->scratch_bytes = sp.total;
     out->ids_bytes = 4 * cap_pad;
     return MPMQ_OK;
@@ -340,14 +336,13 @@ mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params, co
     c->params = *params;
     c->dim = c->ds.dim;
     c->W = c->ds.W;
-    c->wm = c->W < 16 ? 16 : 32;
     c->record_bits = bits;
     c->cap = capacity;
     c->cap_pad = sz.capacity_padded;
     c->stream = (hipStream_t)hip_stream;
     c->words = (uint32_t *)buffers->packed;
-    c->grid[0] = (float4 *)buffers->grid_a;
-    c->grid[1] = (float4 *)buffers->grid_b;
+    c->grid[0] = (GNode *)buffers->grid_a;
+    c->grid[1] = (GNode *)buffers->grid_b;
     c->scratch = (char *)buffers->scratch;
     c->ids = (uint32_t *)buffers->ids;
     c->sp = plan_scratch(c->dim, c->dp.res, c->cap_pad);
@@ -356,6 +351,8 @@ mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params, co
     if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.flags, 0, 4 * 2 * c->sp.nblocks, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.stats, 0, 8 * ST_COUNT, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.misc, 0, 256, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->scratch + c->sp.scheme, &c->ds, sizeof(DevScheme), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         g_last_error = std::string("create: ") + hipGetErrorString(e);
         delete c;
@@ -381,7 +378,7 @@ mpmq_status mpmq_encode(mpmq_ctx *c, const float *x, const float *v, const float
     if (n > 0 && (!x || !v || !C || !F)) return fail(c, MPMQ_EINVAL, "x, v, C and F are required");
     {
         Timed t(c, "encode");
-        HIPCHK(c, launch_encode(c->dim, c->wm, c->ds, x, v, C, F, n, c->cap_pad, c->words, c->ids,
+        HIPCHK(c, launch_encode(c->dim, c->wm, c->dscheme(), x, v, C, F, n, c->cap_pad, c->words, c->ids,
                                 (uint32_t)c->step, 2u, c->stats(), c->stream), "encode");
     }
     c->n = n;
@@ -394,7 +391,7 @@ mpmq_status mpmq_decode(mpmq_ctx *c, float *x, float *v, float *C, float *F) {
     if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
     if (!c->encoded) return fail(c, MPMQ_ESTATE, "decode before encode");
     Timed t(c, "decode");
-    HIPCHK(c, launch_decode(c->dim, c->wm, c->ds, c->words, c->n, c->cap_pad, x, v, C, F, c->stream), "decode");
+    HIPCHK(c, launch_decode(c->dim, c->wm, c->dscheme(), c->words, c->n, c->cap_pad, x, v, C, F, c->stream), "decode");
     return MPMQ_OK;
 }
 
@@ -435,7 +432,7 @@ mpmq_status mpmq_step(mpmq_ctx *c, int32_t n_substeps) {
         }
         if (!c->p2g_ready) {
             Timed t(c, "p2g");
-            HIPCHK(c, launch_p2g(c->dim, c->wm, c->ds, c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+            HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                                  c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st), "p2g");
         }
         {
@@ -446,9 +443,9 @@ mpmq_status mpmq_step(mpmq_ctx *c, int32_t n_substeps) {
         const bool next_sorts = S > 0 && ((s + 1) % S) == 0;
         {
             Timed t(c, "substep");
-            HIPCHK(c, launch_substep(c->dim, c->wm, c->ds, c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+            HIPCHK(c, launch_substep(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                                      c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
-                                     next_sorts ? 0 : 1, 1, c->stats(), st), "substep");
+                                     next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st), "substep");
         }
         c->p2g_ready = !next_sorts;
         c->step = s + 1;
@@ -486,6 +483,13 @@ mpmq_status mpmq_reset_stats(mpmq_ctx *c) {
     HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(c->stats()), 0u, 2 * ST_COUNT, c->stream), "reset stats");
     c->steps_taken = 0;
     c->sorts = 0;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_set_stats(mpmq_ctx *c, int32_t level) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    if (level < 0 || level > 1) return fail(c, MPMQ_EINVAL, "stats level must be 0 or 1");
+    c->stats_level = level;
     return MPMQ_OK;
 }
 

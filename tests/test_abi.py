@@ -40,7 +40,7 @@ def test_query_sizes_record_widths():
     assert f3["packed_bytes"] == 96 * 300_000_000
     assert mq.mpmq_query_sizes(WL.scheme_c1(3, True), WL.c2()["params"], 1 << 20)["words_per_particle"] == 13
     # 512^3 grid of float4 nodes
-    assert s3["grid_bytes"] == 16 * 512 ** 3
+    assert s3["grid_bytes"] == 32 * 512 ** 3  # 512^3 nodes of 4 int64 fixed-point sums
     assert s3["capacity_padded"] % 256 == 0
 
 
