@@ -81,6 +81,10 @@ def lib():
         L.orc_sim_step_count.argtypes = [P]
         L.orc_sim_step_count.restype = ct.c_int64
         L.orc_sim_free.argtypes = [P]
+        L.orc_step_exact.argtypes = [ct.POINTER(_Params), ct.c_int64, P, P]
+        L.orc_step_vjp.argtypes = [ct.POINTER(_Params), ct.c_int64, P, P, P]
+        L.orc_objective.argtypes = [ct.POINTER(_Params), ct.c_int64, P, ct.c_int, ct.c_int,
+                                    ct.POINTER(ct.c_double), P]
         _lib = L
     return _lib
 
@@ -291,3 +295,68 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ adjoint
+# A "state" here is one float64 array of shape [2d + 2d^2, n]: rows x, v, C, F.
+
+def pack_state(x, v, C, F):
+    return np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64) for a in (x, v, C, F)], axis=0))
+
+
+def field_rows(dim):
+    """Row ranges of x, v, C, F in a packed state."""
+    d2 = dim * dim
+    return {"x": (0, dim), "v": (dim, 2 * dim), "C": (2 * dim, 2 * dim + d2), "F": (2 * dim + d2, 2 * dim + 2 * d2)}
+
+
+def step_exact(params: dict, state):
+    st = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros_like(st)
+    if lib().orc_step_exact(ct.byref(make_params(params)), st.shape[1], _ptr(st), _ptr(out)):
+        raise MemoryError("oracle step failed")
+    return out
+
+
+def step_vjp(params: dict, state, lam_out):
+    st = np.ascontiguousarray(state, dtype=np.float64)
+    lo = np.ascontiguousarray(lam_out, dtype=np.float64)
+    li = np.zeros_like(st)
+    if lib().orc_step_vjp(ct.byref(make_params(params)), st.shape[1], _ptr(st), _ptr(lo), _ptr(li)):
+        raise MemoryError("oracle vjp failed")
+    return li
+
+
+OBJECTIVES = {"com": 0, "ke": 1}
+
+
+def objective(params: dict, state, kind="com", axis=1):
+    st = np.ascontiguousarray(state, dtype=np.float64)
+    lam = np.zeros_like(st)
+    z = ct.c_double()
+    lib().orc_objective(ct.byref(make_params(params)), st.shape[1], _ptr(st), OBJECTIVES[kind], axis,
+                        ct.byref(z), _ptr(lam))
+    return z.value, lam
+
+
+def adjoint(params: dict, states, kind="com", axis=1):
+    """Backpropagation through a recorded trajectory (Sec. 6, Eqs. 12-13).
+
+    states[t] is the stored state the substep t -> t+1 started from
+    (t = 0..T).  Returns z, G[field] = sum over t = 0..T, particles and
+    components of d z / d e (the sensitivity to an additive error stored at
+    step t, the adjoint of the stored state), and g[field] = the sum of its
+    squares (the accumulated squared gradient of Eq. 8)."""
+    dim = params["dim"]
+    rows = field_rows(dim)
+    T = len(states) - 1
+    z, lam = objective(params, states[T], kind, axis)
+    G = {f: 0.0 for f in rows}
+    g = {f: 0.0 for f in rows}
+    for t in range(T, -1, -1):
+        for f, (a, b) in rows.items():
+            G[f] += float(lam[a:b].sum())
+            g[f] += float((lam[a:b] ** 2).sum())
+        if t > 0:
+            lam = step_vjp(params, states[t - 1], lam)
+    return z, G, g

@@ -8,7 +8,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["codec.c", "mpm.c"]
+SOURCES = ["codec.c", "mpm.c", "adjoint.c"]
 OUT = os.path.join(HERE, "liboracle.so")
 
 

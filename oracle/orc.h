@@ -79,6 +79,13 @@ int  orc_g2p(const orc_params *p, int64_t n, const double *x, const double *F,
              double *F_new);
 int  orc_sort_order(const orc_params *p, int64_t n, const double *x, int64_t *order);
 
+/* ---- adjoint (adjoint.c): state = x[d][n], v[d][n], C[d*d][n], F[d*d][n] ---- */
+int  orc_step_exact(const orc_params *p, int64_t n, const double *in, double *out);
+int  orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double *lam_out,
+                  double *lam_in);
+int  orc_objective(const orc_params *p, int64_t n, const double *st, int objective, int axis,
+                   double *z, double *lam);
+
 typedef struct orc_sim orc_sim;
 orc_sim *orc_sim_new(const orc_scheme *s, const orc_params *p, int64_t n,
                      const uint32_t *words);
