@@ -191,11 +191,64 @@ typedef struct { char name[32]; int64_t launches; double total_ms; } mpmq_kernel
 mpmq_status mpmq_set_timing(mpmq_ctx *ctx, int32_t enable);
 mpmq_status mpmq_kernel_times(mpmq_ctx *ctx, mpmq_kernel_time *out, int32_t max, int32_t *count);
 
-/* Adjoint of the quantized substep (per-field error sensitivities, Eqs.
- * 8, 12-13).  Not provided by this build: returns MPMQ_ENOTIMPL. */
-typedef struct { int32_t objective; int32_t axis; int32_t steps; int32_t checkpoint_every; } mpmq_adjoint_spec;
-mpmq_status mpmq_adjoint(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, double *G_per_field,
-                         double *g_per_field);
+/* ---- Adjoint (Sec. 6, Eqs. 8, 12-13) ----
+ *
+ * Reverse-mode gradient of an objective z of the final state through
+ * `steps` quantized substeps.  The quantization error of every stored
+ * state is treated as an additive perturbation e_t (Eq. 1), so
+ * d z / d e_t = lambda_t, the adjoint of the stored state s_t, with
+ * lambda_t = (d F(s_t) / d s_t)^T lambda_{t+1} (Eqs. 12-13).  Per field h
+ * (x, v, C, F) the call returns G_h = sum over t = 0..T, particles and
+ * components of lambda and g_h = the sum of its squares, the accumulated
+ * squared gradient of Eq. 8 that the scheme solver of Alg. 1 consumes.
+ *
+ * Forward: from the current stored state s_0 (sorted first if a sort is
+ * pending; lambda rows then follow the sorted slots, see lambda0 below),
+ * `steps` substeps exactly as mpmq_step computes them, except that no
+ * re-sort happens inside the horizon (so the slot of every particle is
+ * fixed and the trajectory equals mpmq_step's for sort_every = 0).  The
+ * context ends at s_T with the step counter advanced by `steps`, as after
+ * mpmq_step; encoder statistics count the forward once.
+ *
+ * Backward: states are recovered by re-running the forward from stored
+ * checkpoints (the forward is bit-reproducible):
+ *   checkpoint_every = K >= 1: checkpoints every K steps, then every state
+ *     of one K-step segment at a time (memory: ceil(T/K) + K states);
+ *   checkpoint_every = 0: bisection (Sec. 6, Fig. 14): checkpoints on the
+ *     path from the root of a binary tree over the steps to the current
+ *     step, O(log T) states, O(T log T) recomputed substeps.
+ *
+ * objective: 0 = centre of mass along `axis` (mean over particles of x_axis),
+ *            1 = kinetic energy (sum of m_p |v|^2 / 2). */
+typedef struct {
+    int32_t objective;
+    int32_t axis;             /* 0 <= axis < dim (objective 0 only) */
+    int32_t steps;            /* T >= 0 */
+    int32_t checkpoint_every; /* K >= 1, or 0 for bisection */
+} mpmq_adjoint_spec;
+
+typedef struct {
+    double z;           /* objective at s_T */
+    double G[4];        /* per field (x, v, C, F): sum of lambda over t, particles, components */
+    double g[4];        /* per field: sum of lambda^2 (Eq. 8 g_h) */
+    double lo[4], hi[4];/* per field: min / max stored component value over s_0..s_T (Alg. 1 ranges) */
+    int64_t recomputed; /* substeps re-run to recover states */
+    int64_t states;     /* states held in the workspace at most */
+} mpmq_adjoint_result;
+
+/* Workspace bytes mpmq_adjoint needs for spec at the current particle count. */
+mpmq_status mpmq_adjoint_workspace(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, int64_t *bytes);
+
+/* Runs the forward and the adjoint described above on the context stream
+ * and synchronizes it.  workspace: caller-owned device memory of at least
+ * mpmq_adjoint_workspace bytes, 256-byte aligned, borrowed for the call.
+ * lambda0 (optional, device, (2d + 2d^2) * n float32): lambda_0 in
+ * component-major rows x[d], v[d], C[d*d], F[d*d], column = the particle's
+ * index at mpmq_encode (the slot when the context has no ids buffer).
+ * Errors: EINVAL (bad spec / NULL out), ENOMEM (workspace too small),
+ * ESTATE (before encode), EDEVICE. */
+mpmq_status mpmq_adjoint(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
+                         float *lambda0, mpmq_adjoint_result *out);
 
 const char *mpmq_error_string(mpmq_status status);
 /* Last error message of ctx (or of the calling thread's last failed

@@ -339,24 +339,33 @@ def objective(params: dict, state, kind="com", axis=1):
     return z.value, lam
 
 
-def adjoint(params: dict, states, kind="com", axis=1):
+def adjoint_full(params: dict, states, kind="com", axis=1):
     """Backpropagation through a recorded trajectory (Sec. 6, Eqs. 12-13).
 
     states[t] is the stored state the substep t -> t+1 started from
-    (t = 0..T).  Returns z, G[field] = sum over t = 0..T, particles and
-    components of d z / d e (the sensitivity to an additive error stored at
-    step t, the adjoint of the stored state), and g[field] = the sum of its
-    squares (the accumulated squared gradient of Eq. 8)."""
+    (t = 0..T), all with the same particle order.  Returns z, and per field
+    G = sum over t = 0..T, particles and components of d z / d e (the
+    sensitivity to an additive error stored at step t, the adjoint of the
+    stored state), g = the sum of its squares (the accumulated squared
+    gradient of Eq. 8), A = the sum of its absolute values, and lambda_0."""
     dim = params["dim"]
     rows = field_rows(dim)
     T = len(states) - 1
     z, lam = objective(params, states[T], kind, axis)
     G = {f: 0.0 for f in rows}
     g = {f: 0.0 for f in rows}
+    A = {f: 0.0 for f in rows}
     for t in range(T, -1, -1):
         for f, (a, b) in rows.items():
             G[f] += float(lam[a:b].sum())
             g[f] += float((lam[a:b] ** 2).sum())
+            A[f] += float(np.abs(lam[a:b]).sum())
         if t > 0:
             lam = step_vjp(params, states[t - 1], lam)
+    return z, G, g, A, lam
+
+
+def adjoint(params: dict, states, kind="com", axis=1):
+    """z, G and g of adjoint_full."""
+    z, G, g, _, _ = adjoint_full(params, states, kind, axis)
     return z, G, g

@@ -78,6 +78,15 @@ class mpmq_adjoint_spec(ct.Structure):
                 ("checkpoint_every", ct.c_int32)]
 
 
+class mpmq_adjoint_result(ct.Structure):
+    _fields_ = [("z", ct.c_double), ("G", ct.c_double * 4), ("g", ct.c_double * 4),
+                ("lo", ct.c_double * 4), ("hi", ct.c_double * 4), ("recomputed", ct.c_int64),
+                ("states", ct.c_int64)]
+
+
+OBJECTIVES = {"com": 0, "ke": 1}
+
+
 _lib = None
 
 
@@ -107,7 +116,8 @@ def load(path: str = LIB_PATH):
         "mpmq_set_stats": [P, ct.c_int32],
         "mpmq_set_timing": [P, ct.c_int32],
         "mpmq_kernel_times": [P, ct.POINTER(mpmq_kernel_time), ct.c_int32, ct.POINTER(ct.c_int32)],
-        "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, P],
+        "mpmq_adjoint_workspace": [P, ct.POINTER(mpmq_adjoint_spec), ct.POINTER(ct.c_int64)],
+        "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, ct.c_int64, P, ct.POINTER(mpmq_adjoint_result)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -124,7 +134,7 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
             "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
-            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint", "mpmq_error_string",
+            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_error_string",
             "mpmq_last_error"]
 
 
@@ -290,14 +300,36 @@ class Context:
             return {}
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(cnt.value, 32))}
 
-    def adjoint(self, spec=None):
-        import numpy as np
-        G = np.zeros(4)
-        g = np.zeros(4)
-        s = mpmq_adjoint_spec(0, 0, 0, 8) if spec is None else spec
-        st = load().mpmq_adjoint(self._h, ct.byref(s), G.ctypes.data_as(ct.c_void_p), g.ctypes.data_as(ct.c_void_p))
-        _check(st, self._h)
-        return G, g
+    def adjoint_workspace_bytes(self, steps, checkpoint_every=8, objective="com", axis=1):
+        s = mpmq_adjoint_spec(OBJECTIVES[objective], int(axis), int(steps), int(checkpoint_every))
+        b = ct.c_int64()
+        _check(load().mpmq_adjoint_workspace(self._h, ct.byref(s), ct.byref(b)), self._h)
+        return b.value
+
+    def adjoint(self, steps, objective="com", axis=1, checkpoint_every=8, want_lambda0=False):
+        """Forward `steps` substeps from the current state and back-propagate
+        (mpmq_adjoint).  Returns a dict with z, G and g per field (x, v, C, F),
+        the per-field value ranges lo / hi, recomputed substeps, states held
+        and, with want_lambda0, lambda_0 as a [2d + 2d^2, n] float32 tensor in
+        encode order."""
+        import torch
+        s = mpmq_adjoint_spec(OBJECTIVES[objective], int(axis), int(steps), int(checkpoint_every))
+        b = ct.c_int64()
+        L = load()
+        _check(L.mpmq_adjoint_workspace(self._h, ct.byref(s), ct.byref(b)), self._h)
+        ws = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
+        rows = 2 * self.dim + 2 * self.dim * self.dim
+        lam0 = torch.empty((rows, self.n), dtype=torch.float32, device=self.device) if want_lambda0 else None
+        res = mpmq_adjoint_result()
+        _check(L.mpmq_adjoint(self._h, ct.byref(s), ct.c_void_p(ws.data_ptr()), int(b.value),
+                              ct.c_void_p(lam0.data_ptr()) if lam0 is not None else None, ct.byref(res)), self._h)
+        names = ["x", "v", "C", "F"]
+        out = {"z": res.z, "G": {names[i]: res.G[i] for i in range(4)}, "g": {names[i]: res.g[i] for i in range(4)},
+               "lo": {names[i]: res.lo[i] for i in range(4)}, "hi": {names[i]: res.hi[i] for i in range(4)},
+               "recomputed": res.recomputed, "states": res.states, "workspace_bytes": b.value}
+        if lam0 is not None:
+            out["lambda0"] = lam0
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
@@ -310,3 +342,48 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class QuantizedRollout:
+    """torch.autograd.Function over `steps` quantized substeps.
+
+    rollout(ctx, x, v, C, F) encodes (x, v, C, F) into the context, runs
+    the forward and the hand-written adjoint (mpmq_adjoint) and returns the
+    objective z as a 0-d float64 tensor; z.backward() delivers lambda_0 to the
+    inputs (the quantization of the stored states enters as an additive
+    error, so the encode is passed straight through).  G and g of the run are
+    left in ctx.last_adjoint."""
+
+    _fn = None
+
+    @classmethod
+    def function(cls):
+        if cls._fn is None:
+            import torch
+
+            class _Rollout(torch.autograd.Function):
+                @staticmethod
+                def forward(fctx, handle, steps, objective, axis, checkpoint_every, x, v, C, F):
+                    handle.encode(x, v, C, F)
+                    res = handle.adjoint(steps, objective=objective, axis=axis, checkpoint_every=checkpoint_every,
+                                         want_lambda0=True)
+                    handle.last_adjoint = res
+                    d = handle.dim
+                    lam = res["lambda0"]
+                    fctx.save_for_backward(lam[:d], lam[d:2 * d], lam[2 * d:2 * d + d * d], lam[2 * d + d * d:])
+                    return torch.tensor(res["z"], dtype=torch.float64, device=x.device)
+
+                @staticmethod
+                def backward(fctx, gz):
+                    lx, lv, lC, lF = fctx.saved_tensors
+                    s = gz.to(torch.float32)
+                    return (None, None, None, None, None, lx * s, lv * s, lC * s, lF * s)
+
+            cls._fn = _Rollout
+        return cls._fn
+
+
+def rollout(handle: Context, x, v, C, F, steps, objective="com", axis=1, checkpoint_every=8):
+    """Differentiable quantized rollout (see QuantizedRollout)."""
+    return QuantizedRollout.function().apply(handle, int(steps), objective, int(axis), int(checkpoint_every),
+                                             x, v, C, F)

@@ -1,0 +1,602 @@
+// adjoint.hip -- gfx950 adjoint kernels of the quantized MLS-MPM substep
+// (Sec. 6, Eqs. 12-13): lambda_t = (d s'_{t+1} / d s_t)^T lambda_{t+1}, with
+// the quantization error treated as an additive perturbation of the stored
+// state (straight-through), so d z / d e_t = lambda_t.  Their sums over
+// steps, particles and components give the per-field sensitivities G_h and
+// the accumulated squared gradients g_h of Eq. 8.
+//
+// Adjoint state layout: float32 SoA, L = 2d + 2d^2 rows of n:
+// x[d], v[d], C[d*d], F[d*d].  Node adjoints: float4 per node (the grid's
+// block-major node order).
+#include "mpmq_device.hpp"
+
+namespace mpmq {
+
+template <int DIM> constexpr int LROWS() { return 2 * DIM + 2 * DIM * DIM; }
+
+// d w / d x_a for a node with offsets o: inv_dx N'_{o_a}(f_a) prod_{b!=a} N_{o_b}(f_b)
+__device__ __forceinline__ void bspline_d(float f, float inv_dx, float *dw) {
+    dw[0] = -(1.5f - f) * inv_dx;
+    dw[1] = -2.0f * (f - 1.0f) * inv_dx;
+    dw[2] = (f - 0.5f) * inv_dx;
+}
+
+template <int DIM>
+__device__ __forceinline__ float det_f(const float *F) {
+    if constexpr (DIM == 2) return F[0] * F[3] - F[1] * F[2];
+    else
+        return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+               F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+template <int DIM>
+__device__ __forceinline__ void cofactor_f(const float *F, float *Cf) {
+    if constexpr (DIM == 2) {
+        Cf[0] = F[3]; Cf[1] = -F[2]; Cf[2] = -F[1]; Cf[3] = F[0];
+    } else {
+        Cf[0] = F[4] * F[8] - F[5] * F[7];
+        Cf[1] = F[5] * F[6] - F[3] * F[8];
+        Cf[2] = F[3] * F[7] - F[4] * F[6];
+        Cf[3] = F[2] * F[7] - F[1] * F[8];
+        Cf[4] = F[0] * F[8] - F[2] * F[6];
+        Cf[5] = F[1] * F[6] - F[0] * F[7];
+        Cf[6] = F[1] * F[5] - F[2] * F[4];
+        Cf[7] = F[2] * F[3] - F[0] * F[5];
+        Cf[8] = F[0] * F[4] - F[1] * F[3];
+    }
+}
+
+// lamF += (d tau / d F)^T [lt] for tau = 2 mu (F - R) F^T + la J (J-1) I.
+// dR = R Y with Y skew solving S Y + Y S = skew(R^T dF - dF^T R), F = R S;
+// the adjoint of the dR term is -4 mu R Y' with S Y' + Y' S = skew(R^T lt F)
+// (3D: S[y]x + [y]x S = [(tr S I - S) y]x; 2D: S Y + Y S = tr(S) Y).
+template <int DIM>
+__device__ __forceinline__ void stress_vjp(const DevParams &P, const float *F, const float *lt, float *lamF) {
+    constexpr int D2 = DIM * DIM;
+    float R[D2], S[D2], Cf[D2];
+    if constexpr (DIM == 2) polar2(F, R);
+    else polar3(F, R);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) a += R[k * DIM + i] * F[k * DIM + j];
+            S[i * DIM + j] = a;
+        }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = i + 1; j < DIM; ++j) {
+            const float a = 0.5f * (S[i * DIM + j] + S[j * DIM + i]);
+            S[i * DIM + j] = a;
+            S[j * DIM + i] = a;
+        }
+    cofactor_f<DIM>(F, Cf);
+    const float J = det_f<DIM>(F);
+    float tr_lt = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) tr_lt += lt[i * DIM + i];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float a = 0.0f, b = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                a += lt[i * DIM + k] * F[k * DIM + j];
+                b += lt[k * DIM + i] * (F[k * DIM + j] - R[k * DIM + j]);
+            }
+            lamF[i * DIM + j] += 2.0f * P.mu * (a + b) + P.la * (2.0f * J - 1.0f) * tr_lt * Cf[i * DIM + j];
+        }
+    float M[D2];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+#pragma unroll
+                for (int l = 0; l < DIM; ++l) a += R[k * DIM + i] * lt[k * DIM + l] * F[l * DIM + j];
+            M[i * DIM + j] = a;
+        }
+    float Y[D2];
+#pragma unroll
+    for (int i = 0; i < D2; ++i) Y[i] = 0.0f;
+    if constexpr (DIM == 2) {
+        const float b = 0.5f * (M[2] - M[1]);
+        const float tr = S[0] + S[3];
+        const float y = (tr != 0.0f) ? b / tr : 0.0f;
+        Y[1] = -y;
+        Y[2] = y;
+    } else {
+        const float b[3] = {0.5f * (M[7] - M[5]), 0.5f * (M[2] - M[6]), 0.5f * (M[3] - M[1])};
+        const float tr = S[0] + S[4] + S[8];
+        float A[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) A[i] = -S[i];
+        A[0] += tr;
+        A[4] += tr;
+        A[8] += tr;
+        float cof[9];
+        cofactor_f<3>(A, cof);
+        const float dA = det_f<3>(A);
+        float y[3] = {0.0f, 0.0f, 0.0f};
+        if (dA != 0.0f) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) y[i] = (cof[i] * b[0] + cof[3 + i] * b[1] + cof[6 + i] * b[2]) / dA;
+        }
+        Y[1] = -y[2]; Y[2] = y[1];
+        Y[3] = y[2]; Y[5] = -y[0];
+        Y[6] = -y[1]; Y[7] = y[0];
+    }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) a += R[i * DIM + k] * Y[k * DIM + j];
+            lamF[i * DIM + j] += -4.0f * P.mu * a;
+        }
+}
+
+template <int DIM>
+__device__ __forceinline__ void stencil_all(const DevParams &P, const double *xd, int *base, float *fx,
+                                            float (*w)[3], float (*dw)[3]) {
+    stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        bspline(fx[a], w[a]);
+        bspline_d(fx[a], P.inv_dx, dw[a]);
+    }
+}
+
+// G2P backward: from lambda_{t+1} (of x', v', C', F') to the partial lambda_t
+// of x and F, and the node adjoints lambda_v_i (scattered with atomics).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sch, DevParams P,
+                                                const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                const GNode *__restrict__ grid, const float *__restrict__ lin,
+                                                float *__restrict__ lout, float4 *__restrict__ nadj) {
+    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST;
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (p >= n) return;
+    SchemeRef s = scheme_ref(sch);
+    const uint32_t p4 = (uint32_t)p * 4u;
+    double xd[DIM];
+    float F[D2];
+    dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
+    dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+    int base[DIM];
+    float fx[DIM], w[DIM][3], dw[DIM][3];
+    stencil_all<DIM>(P, xd, base, fx, w, dw);
+    const float D = 4.0f * P.inv_dx * P.inv_dx;
+    // recompute C' for the F' adjoint
+    float Cn[D2];
+#pragma unroll
+    for (int c = 0; c < D2; ++c) Cn[c] = 0.0f;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        int ijk[DIM];
+        float wt = 1.0f, d[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            wt *= w[a][o[a]];
+            d[a] = ((float)o[a] - fx[a]) * P.dx;
+        }
+        const float4 g = reinterpret_cast<const float4 *>(grid + node_index<DIM>(ijk, P.nb))[0];
+        const float vi[3] = {g.x, g.y, g.z};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] += D * wt * vi[a] * d[b];
+    }
+    float lx[DIM], lv[DIM], lC[D2], lF[D2], oF[D2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        lx[a] = lin[a * n + p];
+        lv[a] = lin[(DIM + a) * n + p];
+    }
+#pragma unroll
+    for (int c = 0; c < D2; ++c) {
+        lC[c] = lin[(2 * DIM + c) * n + p];
+        lF[c] = lin[(2 * DIM + D2 + c) * n + p];
+    }
+    // F' = (I + dt C') F
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float aF = 0.0f, aC = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const float Mki = ((k == i) ? 1.0f : 0.0f) + P.dt * Cn[k * DIM + i];
+                aF += Mki * lF[k * DIM + j];
+                aC += lF[i * DIM + k] * F[j * DIM + k];
+            }
+            oF[i * DIM + j] = aF;
+            lC[i * DIM + j] += P.dt * aC;
+        }
+    // x' = x + dt v'
+    float ox[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        ox[a] = lx[a];
+        lv[a] += P.dt * lx[a];
+    }
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        int ijk[DIM];
+        float wt = 1.0f, d[DIM], gw[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            wt *= w[a][o[a]];
+            d[a] = ((float)o[a] - fx[a]) * P.dx;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            gw[a] = dw[a][o[a]];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b)
+                if (b != a) gw[a] *= w[b][o[b]];
+        }
+        const int64_t id = node_index<DIM>(ijk, P.nb);
+        const float4 g = reinterpret_cast<const float4 *>(grid + id)[0];
+        const float vi[3] = {g.x, g.y, g.z};
+        float lw = 0.0f;
+        float *na = reinterpret_cast<float *>(nadj + id);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float ld = 0.0f;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) ld += lC[a * DIM + b] * d[b];
+            unsafeAtomicAdd(na + a, wt * (lv[a] + D * ld));
+            lw += lv[a] * vi[a] + D * vi[a] * ld;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) ox[b] -= D * wt * lC[a * DIM + b] * vi[a];
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ox[a] += gw[a] * lw;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        lout[a * n + p] = ox[a];
+        lout[(DIM + a) * n + p] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < D2; ++c) {
+        lout[(2 * DIM + c) * n + p] = 0.0f;
+        lout[(2 * DIM + D2 + c) * n + p] = oF[c];
+    }
+}
+
+// Grid backward: v_i = mom_i / m_i + dt g (components zeroed by the wall
+// rule carry no derivative).  In place: (lambda_v, -) -> (lambda_mom, lambda_m).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_adj_grid(DevParams P, const GNode *__restrict__ grid,
+                                                 float4 *__restrict__ nadj, int64_t nodes) {
+    constexpr int B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
+    const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (id >= nodes) return;
+    const float4 g = reinterpret_cast<const float4 *>(grid + id)[0];
+    const float4 la = nadj[id];
+    float out[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float m = g.w;  // physical node mass (0: no particle touched it)
+    if (m > 0.0f) {
+        const int64_t blk = id >> (DIM * L);
+        const int l = (int)(id & ((1 << (DIM * L)) - 1));
+        int ijk[3];
+        ijk[0] = (int)(blk % P.nb) * B + (l & (B - 1));
+        if constexpr (DIM == 3) {
+            ijk[1] = (int)((blk / P.nb) % P.nb) * B + ((l >> L) & (B - 1));
+            ijk[2] = (int)(blk / ((int64_t)P.nb * P.nb)) * B + (l >> (2 * L));
+        } else {
+            ijk[1] = (int)(blk / P.nb) * B + (l >> L);
+        }
+        const float vi[3] = {g.x, g.y, g.z}, lv[3] = {la.x, la.y, la.z};
+        float lm = 0.0f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const bool wall = (ijk[a] < P.bound || ijk[a] >= P.res - P.bound) && vi[a] == 0.0f;
+            if (wall) continue;
+            out[a] = lv[a] / m;
+            lm -= lv[a] * (vi[a] - P.dt * P.g[a]) / m;
+        }
+        out[3] = lm;
+    }
+    nadj[id] = make_float4(out[0], out[1], out[2], out[3]);
+}
+
+// P2G backward: gathers (lambda_mom_i, lambda_m_i) and adds the partial
+// lambda_t of x, v, C and F (stress through its VJP).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_adj_p2g(const DevScheme *__restrict__ sch, DevParams P,
+                                                const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                const float4 *__restrict__ nadj, float *__restrict__ lout) {
+    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST;
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (p >= n) return;
+    SchemeRef s = scheme_ref(sch);
+    const uint32_t p4 = (uint32_t)p * 4u;
+    double xd[DIM];
+    float v[DIM], C[D2], F[D2];
+    dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
+    dec_field<DIM, 1, float>(&s->f[1], words, cap, p4, v);
+    dec_field<DIM, 2, float>(&s->f[2], words, cap, p4, C);
+    dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+    int base[DIM];
+    float fx[DIM], w[DIM][3], dw[DIM][3];
+    stencil_all<DIM>(P, xd, base, fx, w, dw);
+    // A = -dt V D tau + m C  (physical units: p_mass * (stress_over_m tau + C))
+    float R[D2];
+    if constexpr (DIM == 2) polar2(F, R);
+    else polar3(F, R);
+    const float J = det_f<DIM>(F);
+    float A[D2];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float t = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
+            t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
+            A[i * DIM + j] = P.p_mass * (P.stress_over_m * t + C[i * DIM + j]);
+        }
+    const float m = P.p_mass;
+    float lx[DIM], lv[DIM], lA[D2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) lx[a] = lv[a] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < D2; ++c) lA[c] = 0.0f;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        int ijk[DIM];
+        float wt = 1.0f, d[DIM], gw[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            wt *= w[a][o[a]];
+            d[a] = ((float)o[a] - fx[a]) * P.dx;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            gw[a] = dw[a][o[a]];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b)
+                if (b != a) gw[a] *= w[b][o[b]];
+        }
+        const float4 la = nadj[node_index<DIM>(ijk, P.nb)];
+        const float lmo[3] = {la.x, la.y, la.z};
+        float lw = la.w * m;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float Ad = 0.0f;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) Ad += A[a * DIM + b] * d[b];
+            lw += lmo[a] * (m * v[a] + Ad);
+            lv[a] += wt * m * lmo[a];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                lA[a * DIM + b] += wt * lmo[a] * d[b];
+                lx[b] -= wt * lmo[a] * A[a * DIM + b];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) lx[a] += gw[a] * lw;
+    }
+    // A = p_mass stress_over_m tau + p_mass C
+    float lt[D2], lF[D2];
+#pragma unroll
+    for (int c = 0; c < D2; ++c) {
+        lt[c] = P.p_mass * P.stress_over_m * lA[c];
+        lF[c] = 0.0f;
+    }
+    stress_vjp<DIM>(P, F, lt, lF);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        lout[a * n + p] += lx[a];
+        lout[(DIM + a) * n + p] += lv[a];
+    }
+#pragma unroll
+    for (int c = 0; c < D2; ++c) {
+        lout[(2 * DIM + c) * n + p] += m * lA[c];
+        lout[(2 * DIM + D2 + c) * n + p] += lF[c];
+    }
+}
+
+// Objective at the final state: 0 = centre of mass along `axis`, 1 = kinetic
+// energy.  Writes lambda_T and accumulates z (binary64) into acc[0].
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_adj_objective(const DevScheme *__restrict__ sch, DevParams P,
+                                                      const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                      int objective, int axis, float *__restrict__ lout,
+                                                      double *__restrict__ acc) {
+    constexpr int LR = LROWS<DIM>();
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double zc = 0.0;
+    if (p < n) {
+        SchemeRef s = scheme_ref(sch);
+        const uint32_t p4 = (uint32_t)p * 4u;
+#pragma unroll
+        for (int r = 0; r < LR; ++r) lout[r * n + p] = 0.0f;
+        if (objective == 0) {
+            double xd[DIM];
+            dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
+            zc = xd[axis] / (double)n;
+            lout[axis * n + p] = 1.0f / (float)n;
+        } else {
+            double vd[DIM];
+            dec_field<DIM, 1, double>(&s->f[1], words, cap, p4, vd);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                zc += 0.5 * (double)P.p_mass * vd[a] * vd[a];
+                lout[(DIM + a) * n + p] = P.p_mass * (float)vd[a];
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) zc += __shfl_xor(zc, o, 64);
+    if (__lane_id() == 0 && zc != 0.0) atomicAdd(acc, zc);
+}
+
+// G[f] += sum lambda, g[f] += sum lambda^2 over the rows of field f.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_adj_reduce(const float *__restrict__ lam, int64_t n,
+                                                   double *__restrict__ acc) {
+    constexpr int LR = LROWS<DIM>();
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double G[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0};
+    if (p < n) {
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+            const int f = r < DIM ? 0 : r < 2 * DIM ? 1 : r < 2 * DIM + DIM * DIM ? 2 : 3;
+            const double l = (double)lam[r * n + p];
+            G[f] += l;
+            g[f] += l * l;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            G[f] += __shfl_xor(G[f], o, 64);
+            g[f] += __shfl_xor(g[f], o, 64);
+        }
+    }
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            atomicAdd(acc + 1 + f, G[f]);
+            atomicAdd(acc + 5 + f, g[f]);
+        }
+    }
+}
+
+__global__ void k_zero_f4(float4 *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Order-preserving map of float32 to uint32 (for atomic min / max).
+__device__ __forceinline__ uint32_t ord_key(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Per-field minimum and maximum of the stored (decoded) attribute values:
+// rng[f] = min key, rng[4 + f] = max key (ord_key order).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ sch, const uint32_t *__restrict__ words,
+                                                  int64_t cap, int64_t n, uint32_t *__restrict__ rng) {
+    constexpr int D2 = DIM * DIM;
+    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
+    uint32_t lo[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[4] = {0u, 0u, 0u, 0u};
+    if (p < n) {
+        SchemeRef s = scheme_ref(sch);
+        const uint32_t p4 = (uint32_t)p * 4u;
+        double xd[DIM];
+        float v[DIM], C[D2], F[D2];
+        dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
+        dec_field<DIM, 1, float>(&s->f[1], words, cap, p4, v);
+        dec_field<DIM, 2, float>(&s->f[2], words, cap, p4, C);
+        dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const uint32_t kx = ord_key((float)xd[a]), kv = ord_key(v[a]);
+            lo[0] = min(lo[0], kx); hi[0] = max(hi[0], kx);
+            lo[1] = min(lo[1], kv); hi[1] = max(hi[1], kv);
+        }
+#pragma unroll
+        for (int c = 0; c < D2; ++c) {
+            const uint32_t kc = ord_key(C[c]), kf = ord_key(F[c]);
+            lo[2] = min(lo[2], kc); hi[2] = max(hi[2], kc);
+            lo[3] = min(lo[3], kf); hi[3] = max(hi[3], kf);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[f] = min(lo[f], (uint32_t)__shfl_xor((int)lo[f], o, 64));
+            hi[f] = max(hi[f], (uint32_t)__shfl_xor((int)hi[f], o, 64));
+        }
+    }
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            atomicMin(rng + f, lo[f]);
+            atomicMax(rng + 4 + f, hi[f]);
+        }
+    }
+}
+
+// out[r * n + ids[p]] = lam[r * n + p]: rows back into the order of the
+// particles at encode time.
+__global__ void k_adj_unpermute(const float *__restrict__ lam, const uint32_t *__restrict__ ids, int64_t n,
+                                int rows, float *__restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t q = ids[p];
+    if (q >= n) return;
+    for (int r = 0; r < rows; ++r) out[r * n + q] = lam[r * n + p];
+}
+
+static dim3 agrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
+
+hipError_t launch_adj_objective(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
+                                int64_t n, int objective, int axis, float *lam, double *acc, hipStream_t st) {
+    if (dim == 3)
+        hipLaunchKernelGGL(k_adj_objective<3>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, objective, axis, lam, acc);
+    else
+        hipLaunchKernelGGL(k_adj_objective<2>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, objective, axis, lam, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
+                           int64_t n, const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_f4, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 65536)), dim3(256), 0, st,
+                       nadj, nodes);
+    if (dim == 3) {
+        hipLaunchKernelGGL(k_adj_g2p<3>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, grid, lin, lout, nadj);
+        hipLaunchKernelGGL(k_adj_grid<3>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
+        hipLaunchKernelGGL(k_adj_p2g<3>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, nadj, lout);
+    } else {
+        hipLaunchKernelGGL(k_adj_g2p<2>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, grid, lin, lout, nadj);
+        hipLaunchKernelGGL(k_adj_grid<2>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
+        hipLaunchKernelGGL(k_adj_p2g<2>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, nadj, lout);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(int dim, const float *lam, int64_t n, double *acc, hipStream_t st) {
+    if (dim == 3) hipLaunchKernelGGL(k_adj_reduce<3>, agrid(n), dim3(WG), 0, st, lam, n, acc);
+    else hipLaunchKernelGGL(k_adj_reduce<2>, agrid(n), dim3(WG), 0, st, lam, n, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_range(int dim, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n, uint32_t *rng,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (dim == 3) hipLaunchKernelGGL(k_adj_range<3>, agrid(n), dim3(WG), 0, st, s, words, cap, n, rng);
+    else hipLaunchKernelGGL(k_adj_range<2>, agrid(n), dim3(WG), 0, st, s, words, cap, n, rng);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_unpermute(const float *lam, const uint32_t *ids, int64_t n, int rows, float *out,
+                                hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_unpermute, agrid(n), dim3(WG), 0, st, lam, ids, n, rows, out);
+    return hipGetLastError();
+}
+
+}  // namespace mpmq

@@ -120,4 +120,18 @@ hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &
                           const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, uint32_t step,
                           int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st);
 
+// Adjoint (adjoint.hip).  lam buffers: float32 rows x[d], v[d], C[d*d],
+// F[d*d] of n each; nadj: one float4 per grid node; acc: binary64 z, G[4],
+// g[4]; rng: uint32 order keys min[4], max[4].
+hipError_t launch_adj_objective(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
+                                int64_t n, int objective, int axis, float *lam, double *acc, hipStream_t st);
+hipError_t launch_adj_step(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
+                           int64_t n, const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
+                           hipStream_t st);
+hipError_t launch_adj_reduce(int dim, const float *lam, int64_t n, double *acc, hipStream_t st);
+hipError_t launch_adj_range(int dim, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n, uint32_t *rng,
+                            hipStream_t st);
+hipError_t launch_adj_unpermute(const float *lam, const uint32_t *ids, int64_t n, int rows, float *out,
+                                hipStream_t st);
+
 }  // namespace mpmq

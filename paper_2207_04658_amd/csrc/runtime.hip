@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -275,6 +276,234 @@ mpmq_status do_sort(mpmq_ctx *c) {
     return MPMQ_OK;
 }
 
+// One substep on c->words: sort when due (allow_sort), P2G unless the
+// previous substep already scattered this state, grid update, fused
+// G2P / update / encode / store / P2G kernel.
+mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
+    hipStream_t st = c->stream;
+    const int S = c->params.sort_every;
+    const int64_t s = c->step;
+    const int cur = (int)(s & 1), nxt = cur ^ 1;
+    const bool need_sort = allow_sort && (!c->sorted || (S > 0 && s % S == 0 && c->sorted_at != s));
+    if (need_sort) {
+        if (c->p2g_ready) {
+            Timed t(c, "clear");
+            HIPCHK(c, launch_clear_touched(c->dim, c->grid[cur], c->flags(cur), c->sp.nblocks, st), "clear");
+            c->p2g_ready = false;
+        }
+        mpmq_status r = do_sort(c);
+        if (r != MPMQ_OK) return r;
+        c->sorted = true;
+        c->sorted_at = s;
+    }
+    if (!c->p2g_ready) {
+        Timed t(c, "p2g");
+        HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+                             c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st), "p2g");
+    }
+    {
+        Timed t(c, "grid_update");
+        HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[cur], c->grid[nxt], c->flags(cur), c->flags(nxt),
+                                     c->sp.nblocks, c->stats(), st), "grid update");
+    }
+    const bool next_sorts = allow_sort && S > 0 && ((s + 1) % S) == 0;
+    {
+        Timed t(c, "substep");
+        HIPCHK(c, launch_substep(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+                                 c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
+                                 next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st), "substep");
+    }
+    c->p2g_ready = !next_sorts;
+    c->step = s + 1;
+    c->steps_taken += 1;
+    return MPMQ_OK;
+}
+
+// Zeroes both grid buffers (every non-zero node block is flagged) so that
+// the next substep starts with a P2G of c->words.
+mpmq_status reset_grids(mpmq_ctx *c) {
+    for (int i = 0; i < 2; ++i)
+        HIPCHK(c, launch_clear_touched(c->dim, c->grid[i], c->flags(i), c->sp.nblocks, c->stream), "clear grids");
+    c->p2g_ready = false;
+    return MPMQ_OK;
+}
+
+int adj_rows(int dim) { return 2 * dim + 2 * dim * dim; }
+
+// Checkpoint plan of the adjoint: which states the forward pass stores and
+// how many state buffers the backward pass holds at once.
+struct AdjPlan {
+    int64_t T = 0, K = 0;
+    std::vector<int64_t> forward_saves;  // step indices stored by the forward pass
+    int64_t slots = 0;                   // state buffers (excluding the final state)
+};
+
+// Bisection: the forward pass keeps s_0 and the midpoints on the path to the
+// last step; reverse(lo, hi) then needs one new buffer per tree level.
+void bisect_right_path(int64_t lo, int64_t hi, std::vector<int64_t> &out) {
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        out.push_back(mid);
+        lo = mid;
+    }
+}
+
+AdjPlan adj_plan(int64_t T, int64_t K) {
+    AdjPlan p;
+    p.T = T;
+    p.K = K;
+    p.forward_saves.push_back(0);
+    if (T <= 0) {
+        p.slots = 1;
+        return p;
+    }
+    if (K >= 1) {
+        for (int64_t t = K; t < T; t += K) p.forward_saves.push_back(t);
+        p.slots = (int64_t)p.forward_saves.size() + std::min<int64_t>(K, T) - 1;
+    } else {
+        bisect_right_path(0, T, p.forward_saves);
+        int64_t depth = 0;
+        while (((int64_t)1 << depth) < T) ++depth;
+        p.slots = depth + 1;
+    }
+    return p;
+}
+
+struct AdjWork {
+    int64_t state_bytes = 0, lam_bytes = 0, nodes = 0;
+    int64_t off_states = 0, off_final = 0, off_lam = 0, off_nadj = 0, off_acc = 0, off_stats = 0, total = 0;
+};
+
+AdjWork adj_layout(const mpmq_ctx *c, const AdjPlan &plan) {
+    AdjWork w;
+    const int CPB = c->dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
+    w.nodes = c->sp.nblocks * CPB;
+    w.state_bytes = 4 * (int64_t)c->W * c->cap_pad;
+    w.lam_bytes = align256(4 * (int64_t)adj_rows(c->dim) * std::max<int64_t>(c->n, 1));
+    int64_t o = 0;
+    w.off_states = o; o += plan.slots * w.state_bytes;
+    w.off_final = o; o += w.state_bytes;
+    w.off_lam = o; o += 2 * w.lam_bytes;
+    w.off_nadj = o; o = align256(o + 16 * w.nodes);
+    w.off_acc = o; o = align256(o + 8 * 16 + 4 * 8);
+    w.off_stats = o; o = align256(o + 8 * ST_COUNT);
+    w.total = o;
+    return w;
+}
+
+mpmq_status check_spec(mpmq_ctx *c, const mpmq_adjoint_spec *sp) {
+    if (!sp) return fail(c, MPMQ_EINVAL, "spec is NULL");
+    if (sp->objective != 0 && sp->objective != 1) return fail(c, MPMQ_EINVAL, "objective must be 0 (COM) or 1 (KE)");
+    if (sp->objective == 0 && (sp->axis < 0 || sp->axis >= c->dim)) return fail(c, MPMQ_EINVAL, "axis out of range");
+    if (sp->steps < 0) return fail(c, MPMQ_EINVAL, "steps < 0");
+    if (sp->checkpoint_every < 0) return fail(c, MPMQ_EINVAL, "checkpoint_every < 0");
+    return MPMQ_OK;
+}
+
+// Backward driver over a workspace: state buffers handed out from a free
+// list, states recovered by re-running the forward from a stored one.
+struct AdjRun {
+    mpmq_ctx *c;
+    char *ws;
+    AdjWork w;
+    int64_t step0 = 0;
+    std::vector<int> free_slots;
+    std::map<int64_t, int> saved;  // step -> slot, states kept by the forward pass
+    float *lam_cur = nullptr, *lam_nxt = nullptr;
+    int64_t recomputed = 0, live = 0, max_live = 0;
+
+    uint32_t *slot_ptr(int s) { return reinterpret_cast<uint32_t *>(ws + w.off_states + (int64_t)s * w.state_bytes); }
+    uint32_t *final_ptr() { return reinterpret_cast<uint32_t *>(ws + w.off_final); }
+    double *acc() { return reinterpret_cast<double *>(ws + w.off_acc); }
+    uint32_t *rng() { return reinterpret_cast<uint32_t *>(ws + w.off_acc + 8 * 16); }
+    float4 *nadj() { return reinterpret_cast<float4 *>(ws + w.off_nadj); }
+    int64_t state_words() const { return (int64_t)c->W * c->cap_pad; }
+
+    int take() {
+        const int s = free_slots.back();
+        free_slots.pop_back();
+        max_live = std::max<int64_t>(max_live, ++live);
+        return s;
+    }
+    void give(int s) {
+        free_slots.push_back(s);
+        --live;
+    }
+    mpmq_status copy_state(const uint32_t *from, uint32_t *to) {
+        HIPCHK(c, launch_copy_u32(from, to, state_words(), c->stream), "adjoint: state copy");
+        return MPMQ_OK;
+    }
+    // c->words = s_from (taken from `from`), then substeps up to each target
+    // step in ascending order, copying s_t into its slot.
+    mpmq_status advance(const uint32_t *from, int64_t t_from, const std::vector<std::pair<int64_t, int>> &targets) {
+        mpmq_status r = copy_state(from, c->words);
+        if (r != MPMQ_OK) return r;
+        if ((r = reset_grids(c)) != MPMQ_OK) return r;
+        c->step = step0 + t_from;
+        int64_t t = t_from;
+        for (const auto &tg : targets) {
+            while (t < tg.first) {
+                if ((r = substep_once(c, false)) != MPMQ_OK) return r;
+                ++t;
+                ++recomputed;
+            }
+            if ((r = copy_state(c->words, slot_ptr(tg.second))) != MPMQ_OK) return r;
+        }
+        return MPMQ_OK;
+    }
+    // lambda_t from lambda_{t+1} at stored state `words` (s_t).
+    mpmq_status adjoint_step(const uint32_t *words) {
+        mpmq_status r = reset_grids(c);
+        if (r != MPMQ_OK) return r;
+        hipStream_t st = c->stream;
+        HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, words, c->cap_pad, c->items(), c->n_items(),
+                             c->launch_grid, c->grid[0], c->flags(0), c->stats(), st), "adjoint: p2g");
+        HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[0], c->grid[1], c->flags(0), c->flags(1), c->sp.nblocks,
+                                     c->stats(), st), "adjoint: grid update");
+        {
+            Timed tm(c, "adjoint_step");
+            HIPCHK(c, launch_adj_step(c->dim, c->dscheme(), c->dp, words, c->cap_pad, c->n, c->grid[0], w.nodes,
+                                      lam_cur, lam_nxt, nadj(), st), "adjoint: step");
+        }
+        HIPCHK(c, launch_adj_reduce(c->dim, lam_nxt, c->n, acc(), st), "adjoint: reduce");
+        std::swap(lam_cur, lam_nxt);
+        return MPMQ_OK;
+    }
+    // Reverses steps [lo, hi) given s_lo in slot `slot_lo` and lambda_hi in
+    // lam_cur; leaves lambda_lo in lam_cur.
+    mpmq_status reverse_bisect(int64_t lo, int64_t hi, int slot_lo) {
+        if (hi - lo == 1) return adjoint_step(slot_ptr(slot_lo));
+        const int64_t mid = (lo + hi) / 2;
+        int slot_mid;
+        mpmq_status r;
+        auto it = saved.find(mid);
+        if (it != saved.end()) {
+            slot_mid = it->second;
+            saved.erase(it);
+        } else {
+            slot_mid = take();
+            if ((r = advance(slot_ptr(slot_lo), lo, {{mid, slot_mid}})) != MPMQ_OK) return r;
+        }
+        if ((r = reverse_bisect(mid, hi, slot_mid)) != MPMQ_OK) return r;
+        give(slot_mid);
+        return reverse_bisect(lo, mid, slot_lo);
+    }
+    // Uniform checkpoints: segment [a, b) from the stored s_a; all of its
+    // states are recovered, then reversed.
+    mpmq_status reverse_segment(int64_t a, int64_t b, int slot_a) {
+        std::vector<std::pair<int64_t, int>> tg;
+        for (int64_t t = a + 1; t < b; ++t) tg.push_back({t, take()});
+        mpmq_status r;
+        if (!tg.empty() && (r = advance(slot_ptr(slot_a), a, tg)) != MPMQ_OK) return r;
+        for (int64_t t = b - 1; t > a; --t) {
+            const int s = tg[(size_t)(t - a - 1)].second;
+            if ((r = adjoint_step(slot_ptr(s))) != MPMQ_OK) return r;
+            give(s);
+        }
+        return adjoint_step(slot_ptr(slot_a));
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -413,43 +642,9 @@ mpmq_status mpmq_step(mpmq_ctx *c, int32_t n_substeps) {
         c->steps_taken += n_substeps;
         return MPMQ_OK;
     }
-    hipStream_t st = c->stream;
-    const int S = c->params.sort_every;
     for (int32_t it = 0; it < n_substeps; ++it) {
-        const int64_t s = c->step;
-        const int cur = (int)(s & 1), nxt = cur ^ 1;
-        const bool need_sort = !c->sorted || (S > 0 && s % S == 0 && c->sorted_at != s);
-        if (need_sort) {
-            if (c->p2g_ready) {
-                Timed t(c, "clear");
-                HIPCHK(c, launch_clear_touched(c->dim, c->grid[cur], c->flags(cur), c->sp.nblocks, st), "clear");
-                c->p2g_ready = false;
-            }
-            mpmq_status r = do_sort(c);
-            if (r != MPMQ_OK) return r;
-            c->sorted = true;
-            c->sorted_at = s;
-        }
-        if (!c->p2g_ready) {
-            Timed t(c, "p2g");
-            HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
-                                 c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st), "p2g");
-        }
-        {
-            Timed t(c, "grid_update");
-            HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[cur], c->grid[nxt], c->flags(cur), c->flags(nxt),
-                                         c->sp.nblocks, c->stats(), st), "grid update");
-        }
-        const bool next_sorts = S > 0 && ((s + 1) % S) == 0;
-        {
-            Timed t(c, "substep");
-            HIPCHK(c, launch_substep(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
-                                     c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
-                                     next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st), "substep");
-        }
-        c->p2g_ready = !next_sorts;
-        c->step = s + 1;
-        c->steps_taken += 1;
+        mpmq_status r = substep_once(c, true);
+        if (r != MPMQ_OK) return r;
     }
     return MPMQ_OK;
 }
@@ -527,8 +722,129 @@ mpmq_status mpmq_kernel_times(mpmq_ctx *c, mpmq_kernel_time *out, int32_t max, i
     return MPMQ_OK;
 }
 
-mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *, double *, double *) {
-    return fail(c, MPMQ_ENOTIMPL, "adjoint is not provided by this build");
+mpmq_status mpmq_adjoint_workspace(mpmq_ctx *c, const mpmq_adjoint_spec *spec, int64_t *bytes) {
+    if (!c || !bytes) return fail(c, MPMQ_EINVAL, "ctx or bytes is NULL");
+    mpmq_status r = check_spec(c, spec);
+    if (r != MPMQ_OK) return r;
+    *bytes = adj_layout(c, adj_plan(spec->steps, spec->checkpoint_every)).total;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
+                         float *lambda0, mpmq_adjoint_result *out) {
+    if (!c || !out) return fail(c, MPMQ_EINVAL, "ctx or out is NULL");
+    mpmq_status r = check_spec(c, spec);
+    if (r != MPMQ_OK) return r;
+    if (!c->encoded) return fail(c, MPMQ_ESTATE, "adjoint before encode");
+    const int64_t T = spec->steps;
+    const AdjPlan plan = adj_plan(T, spec->checkpoint_every);
+    AdjRun run;
+    run.c = c;
+    run.w = adj_layout(c, plan);
+    if (!workspace || workspace_bytes < run.w.total) return fail(c, MPMQ_ENOMEM, "adjoint workspace too small");
+    if ((uintptr_t)workspace & 255u) return fail(c, MPMQ_EINVAL, "workspace must be 256-byte aligned");
+    std::memset(out, 0, sizeof(*out));
+    hipStream_t st = c->stream;
+    const int64_t n = c->n;
+    const int rows = adj_rows(c->dim);
+    if (n == 0) {
+        c->step += T;
+        c->steps_taken += T;
+        return MPMQ_OK;
+    }
+    run.ws = (char *)workspace;
+    run.step0 = c->step;
+    run.lam_cur = reinterpret_cast<float *>(run.ws + run.w.off_lam);
+    run.lam_nxt = reinterpret_cast<float *>(run.ws + run.w.off_lam + run.w.lam_bytes);
+    for (int s = (int)plan.slots - 1; s >= 0; --s) run.free_slots.push_back(s);
+    HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(run.acc()), 0u, 2 * 16, st), "adjoint: clear");
+    HIPCHK(c, launch_fill_u32(run.rng(), 0xffffffffu, 4, st), "adjoint: clear");
+    HIPCHK(c, launch_fill_u32(run.rng() + 4, 0u, 4, st), "adjoint: clear");
+    // forward: sort once if pending, then T substeps without re-sorting
+    if (!c->sorted) {
+        if (c->p2g_ready) {
+            HIPCHK(c, launch_clear_touched(c->dim, c->grid[c->step & 1], c->flags((int)(c->step & 1)), c->sp.nblocks, st),
+                   "clear");
+            c->p2g_ready = false;
+        }
+        if ((r = do_sort(c)) != MPMQ_OK) return r;
+        c->sorted = true;
+        c->sorted_at = c->step;
+    }
+    size_t save_i = 0;
+    for (int64_t t = 0; t <= T; ++t) {
+        HIPCHK(c, launch_adj_range(c->dim, c->dscheme(), c->words, c->cap_pad, n, run.rng(), st), "adjoint: ranges");
+        if (save_i < plan.forward_saves.size() && plan.forward_saves[save_i] == t) {
+            const int s = run.take();
+            if ((r = run.copy_state(c->words, run.slot_ptr(s))) != MPMQ_OK) return r;
+            run.saved[t] = s;
+            ++save_i;
+        }
+        if (t < T && (r = substep_once(c, false)) != MPMQ_OK) return r;
+    }
+    const int64_t steps_after = c->steps_taken;
+    HIPCHK(c, launch_copy_u32(reinterpret_cast<uint32_t *>(c->stats()), reinterpret_cast<uint32_t *>(run.ws + run.w.off_stats),
+                              2 * ST_COUNT, st), "adjoint: stats");
+    if ((r = run.copy_state(c->words, run.final_ptr())) != MPMQ_OK) return r;
+    // objective at s_T and lambda_T
+    HIPCHK(c, launch_adj_objective(c->dim, c->dscheme(), c->dp, c->words, c->cap_pad, n, spec->objective, spec->axis,
+                                   run.lam_cur, run.acc(), st), "adjoint: objective");
+    HIPCHK(c, launch_adj_reduce(c->dim, run.lam_cur, n, run.acc(), st), "adjoint: reduce");
+    // backward
+    if (T > 0) {
+        if (spec->checkpoint_every >= 1) {
+            const int64_t K = spec->checkpoint_every;
+            const int64_t nseg = (T + K - 1) / K;
+            for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+                const int64_t a = sg * K, b = std::min<int64_t>(a + K, T);
+                const int slot_a = run.saved.at(a);
+                if ((r = run.reverse_segment(a, b, slot_a)) != MPMQ_OK) return r;
+                run.saved.erase(a);
+                run.give(slot_a);
+            }
+        } else {
+            const int slot0 = run.saved.at(0);
+            run.saved.erase(0);
+            if ((r = run.reverse_bisect(0, T, slot0)) != MPMQ_OK) return r;
+            run.give(slot0);
+        }
+    }
+    if (lambda0) {
+        if (c->ids) {
+            HIPCHK(c, launch_adj_unpermute(run.lam_cur, c->ids, n, rows, lambda0, st), "adjoint: lambda0");
+        } else {
+            HIPCHK(c, launch_copy_u32(reinterpret_cast<const uint32_t *>(run.lam_cur), reinterpret_cast<uint32_t *>(lambda0),
+                                      (int64_t)rows * n, st), "adjoint: lambda0");
+        }
+    }
+    // restore s_T, the step counter and the statistics of the forward pass
+    if ((r = run.copy_state(run.final_ptr(), c->words)) != MPMQ_OK) return r;
+    if ((r = reset_grids(c)) != MPMQ_OK) return r;
+    HIPCHK(c, launch_copy_u32(reinterpret_cast<uint32_t *>(run.ws + run.w.off_stats), reinterpret_cast<uint32_t *>(c->stats()),
+                              2 * ST_COUNT, st), "adjoint: stats");
+    c->step = run.step0 + T;
+    c->steps_taken = steps_after;
+    double acc[16];
+    uint32_t rng[8];
+    HIPCHK(c, hipMemcpyAsync(acc, run.acc(), sizeof(acc), hipMemcpyDeviceToHost, st), "adjoint: result");
+    HIPCHK(c, hipMemcpyAsync(rng, run.rng(), sizeof(rng), hipMemcpyDeviceToHost, st), "adjoint: result");
+    HIPCHK(c, hipStreamSynchronize(st), "adjoint: sync");
+    out->z = acc[0];
+    for (int f = 0; f < 4; ++f) {
+        out->G[f] = acc[1 + f];
+        out->g[f] = acc[5 + f];
+        auto unkey = [](uint32_t k) {
+            const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+            float v;
+            std::memcpy(&v, &u, 4);
+            return (double)v;
+        };
+        out->lo[f] = unkey(rng[f]);
+        out->hi[f] = unkey(rng[4 + f]);
+    }
+    out->recomputed = run.recomputed;
+    out->states = run.max_live + 1;
+    return MPMQ_OK;
 }
 
 }  // extern "C"

@@ -19,6 +19,11 @@ Table "large_scale"):
       dt=1e-4, 10 steps; x 3x21-bit fixed, v 3x13-bit shared-exponent float
       (6-bit exponent), F 9x14-bit fixed (F-I), C 9x16-bit fixed, all
       dithered: 378 bits = 12 words = 48 B per particle.
+  c5  3D adjoint scene: one cube of side 0.5 (8 particles per cell, so
+      grid_res^3 particles: 262144 at 64^3), corner (0.25, 0.25, 0.25),
+      velocity = one U(-1,1)^3 drift + a rigid spin with angular velocity
+      U(-2,2)^3 about the cube centre + per-particle U(-0.1,0.1) noise;
+      dt=2e-4, 64 steps, the c2 scheme, no re-sort.
   fp32 layout: the same scene with every field stored as raw float32.
 """
 from __future__ import annotations
@@ -148,6 +153,25 @@ def c2(seed=0, cubes=4, per_cube=262144, grid_res=128, steps=100, sort_every=10)
     sc = scheme_c1(3, True, seed)
     return cubes_scene("c2", seed, grid_res, corners, side, [per_cube] * cubes, vels,
                        2e-4, steps, sc, sort_every)
+
+
+def c5(seed=0, grid_res=64, steps=64):
+    """Adjoint scene (see module docstring); n = grid_res^3 particles."""
+    rng = np.random.default_rng([seed, 5])
+    side = 0.5
+    n = grid_res ** 3
+    corner = np.array([0.25, 0.25, 0.25])
+    x = (corner[:, None] + side * rng.random((3, n))).astype(np.float32)
+    drift = rng.uniform(-1.0, 1.0, 3)
+    omega = rng.uniform(-2.0, 2.0, 3)
+    r = x.astype(np.float64) - (corner + 0.5 * side)[:, None]
+    spin = np.cross(omega[:, None], r, axis=0)
+    v = (drift[:, None] + spin + rng.uniform(-0.1, 0.1, (3, n))).astype(np.float32)
+    _, C, F = rest_state(3, n)
+    sc = scheme_c1(3, True, seed)
+    return {"name": "c5", "scheme": sc, "steps": steps, "n": n,
+            "params": params(3, grid_res, 2e-4, side ** 3 / n, sort_every=0),
+            "state": (x, v, C, F)}
 
 
 C3_TOTAL = 300_000_000
