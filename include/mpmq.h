@@ -231,7 +231,8 @@ typedef struct {
     double z;           /* objective at s_T */
     double G[4];        /* per field (x, v, C, F): sum of lambda over t, particles, components */
     double g[4];        /* per field: sum of lambda^2 (Eq. 8 g_h) */
-    double lo[4], hi[4];/* per field: min / max stored component value over s_0..s_T (Alg. 1 ranges) */
+    double lo[4], hi[4];/* per field: min / max stored component value over s_0..s_T (Alg. 1
+                           ranges; F - I for a REL_IDENTITY field) */
     int64_t recomputed; /* substeps re-run to recover states */
     int64_t states;     /* states held in the workspace at most */
 } mpmq_adjoint_result;
@@ -249,6 +250,36 @@ mpmq_status mpmq_adjoint_workspace(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec,
  * ESTATE (before encode), EDEVICE. */
 mpmq_status mpmq_adjoint(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
                          float *lambda0, mpmq_adjoint_result *out);
+
+/* ---- Automatic quantization solver (Sec. 4, Eqs. 6-10, Alg. 1) ----
+ * Host-only; touches no device.  Per data type h: P_h variables, the
+ * accumulated squared gradient g_h (Eq. 8; mpmq_adjoint's g), the range
+ * width R_h.  Error-bounded (mode 0): smallest sum P_h b_h with
+ * (1/12) sum Delta_h^2 g_h <= (eps z)^2, Delta_h from Eq. 10 and
+ * b_h = ceil(log2(R_h / Delta_h)) as in Alg. 1.  Memory-bounded (mode 1):
+ * least expected error with sum P_h b_h <= eps * 32 sum P_h (Eq. 7);
+ * Delta_h = K sqrt(P_h / g_h) (Lagrange conditions of Eq. 7 under Eq. 8),
+ * b_h = floor(log2(R_h / Delta_h)).  Types with g_h = 0 take min_bits.  Bits
+ * are clamped to [min_bits, max_bits].  Input arrays are host memory of
+ * n_types entries; outputs likewise.  EINVAL on invalid input (the reason:
+ * mpmq_solver_error()). */
+#define MPMQ_SOLVE_MAX_TYPES 16
+enum { MPMQ_SOLVE_ERROR_BOUND = 0, MPMQ_SOLVE_MEMORY_BOUND = 1 };
+typedef struct {
+    int32_t mode, n_types, min_bits, max_bits;
+    double eps;       /* eps_err (relative error of z) or eps_mem (memory fraction of FP32) */
+    double z;         /* reference objective value (error-bounded mode) */
+    const double *P, *g, *R;
+} mpmq_solve_input;
+typedef struct {
+    double *delta;    /* continuous quantization step (INFINITY where g_h = 0) */
+    double *b_cont;   /* continuous bit width log2(R_h / Delta_h) */
+    int32_t *bits;    /* integer bit width */
+    double expected_error; /* (1/12) sum (R_h 2^-bits_h)^2 g_h */
+    double total_bits;     /* sum P_h bits_h */
+} mpmq_solve_output;
+mpmq_status mpmq_solve_scheme(const mpmq_solve_input *in, mpmq_solve_output *out);
+const char *mpmq_solver_error(void);
 
 const char *mpmq_error_string(mpmq_status status);
 /* Last error message of ctx (or of the calling thread's last failed

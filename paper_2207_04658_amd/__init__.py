@@ -85,6 +85,18 @@ class mpmq_adjoint_result(ct.Structure):
 
 
 OBJECTIVES = {"com": 0, "ke": 1}
+SOLVE_MODES = {"error": 0, "memory": 1}
+
+
+class mpmq_solve_input(ct.Structure):
+    _fields_ = [("mode", ct.c_int32), ("n_types", ct.c_int32), ("min_bits", ct.c_int32), ("max_bits", ct.c_int32),
+                ("eps", ct.c_double), ("z", ct.c_double), ("P", ct.POINTER(ct.c_double)),
+                ("g", ct.POINTER(ct.c_double)), ("R", ct.POINTER(ct.c_double))]
+
+
+class mpmq_solve_output(ct.Structure):
+    _fields_ = [("delta", ct.POINTER(ct.c_double)), ("b_cont", ct.POINTER(ct.c_double)),
+                ("bits", ct.POINTER(ct.c_int32)), ("expected_error", ct.c_double), ("total_bits", ct.c_double)]
 
 
 _lib = None
@@ -118,6 +130,7 @@ def load(path: str = LIB_PATH):
         "mpmq_kernel_times": [P, ct.POINTER(mpmq_kernel_time), ct.c_int32, ct.POINTER(ct.c_int32)],
         "mpmq_adjoint_workspace": [P, ct.POINTER(mpmq_adjoint_spec), ct.POINTER(ct.c_int64)],
         "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, ct.c_int64, P, ct.POINTER(mpmq_adjoint_result)],
+        "mpmq_solve_scheme": [ct.POINTER(mpmq_solve_input), ct.POINTER(mpmq_solve_output)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -127,6 +140,8 @@ def load(path: str = LIB_PATH):
     L.mpmq_error_string.restype = ct.c_char_p
     L.mpmq_last_error.argtypes = [P]
     L.mpmq_last_error.restype = ct.c_char_p
+    L.mpmq_solver_error.argtypes = []
+    L.mpmq_solver_error.restype = ct.c_char_p
     _lib = L
     return L
 
@@ -134,7 +149,7 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
             "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
-            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_error_string",
+            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_solve_scheme", "mpmq_solver_error", "mpmq_error_string",
             "mpmq_last_error"]
 
 
@@ -342,6 +357,51 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def solve_scheme(P, g, R, mode="error", eps=1e-3, z=1.0, min_bits=1, max_bits=32):
+    """mpmq_solve_scheme (host only).  Returns dict(delta, b_cont, bits,
+    expected_error, total_bits) with lists per type."""
+    H = len(P)
+    arr = ct.c_double * H
+    Pa, ga, Ra = arr(*map(float, P)), arr(*map(float, g)), arr(*map(float, R))
+    d, b, bits = arr(), arr(), (ct.c_int32 * H)()
+    inp = mpmq_solve_input(SOLVE_MODES[mode], H, int(min_bits), int(max_bits), float(eps), float(z),
+                           Pa, ga, Ra)
+    out = mpmq_solve_output(d, b, bits, 0.0, 0.0)
+    st = load().mpmq_solve_scheme(ct.byref(inp), ct.byref(out))
+    if st != 0:
+        raise MpmqError(st, load().mpmq_solver_error().decode())
+    return {"delta": list(d), "b_cont": list(b), "bits": list(bits), "expected_error": out.expected_error,
+            "total_bits": out.total_bits}
+
+
+def auto_scheme(base: dict, adjoint_result: dict, n: int, mode="error", eps=1e-3, range_factor=2.0,
+                min_bits=1, max_bits=32):
+    """Alg. 1: a fixed-point scheme from an adjoint run (normally of the
+    full-precision layout): per field, the recorded value range widened by
+    `range_factor` about its centre, and the bits of mpmq_solve_scheme.
+    Placement order, dither, REL_IDENTITY and the seed follow `base`."""
+    dim = base["dim"]
+    names = ["x", "v", "C", "F"]
+    ncomp = {"x": dim, "v": dim, "C": dim * dim, "F": dim * dim}
+    lo, hi = {}, {}
+    for f in names:
+        mid = 0.5 * (adjoint_result["lo"][f] + adjoint_result["hi"][f])
+        half = 0.5 * (adjoint_result["hi"][f] - adjoint_result["lo"][f]) * range_factor
+        half = max(half, 1e-30)
+        lo[f], hi[f] = mid - half, mid + half
+    P = [float(n * ncomp[f]) for f in names]
+    g = [adjoint_result["g"][f] for f in names]
+    R = [hi[f] - lo[f] for f in names]
+    sol = solve_scheme(P, g, R, mode=mode, eps=eps, z=adjoint_result["z"], min_bits=min_bits, max_bits=max_bits)
+    fields = []
+    for fs in base["fields"]:
+        i = names.index(fs["field"])
+        fields.append({"field": fs["field"], "kind": "fixed", "bits": sol["bits"][i], "lo": lo[fs["field"]],
+                       "hi": hi[fs["field"]], "dither": fs.get("dither", False),
+                       "rel_identity": fs.get("rel_identity", False), "exp_bits": 0})
+    return {"dim": dim, "seed": base.get("seed", 0), "fields": fields}, sol
 
 
 class QuantizedRollout:

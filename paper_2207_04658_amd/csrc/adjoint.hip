@@ -492,7 +492,8 @@ __device__ __forceinline__ uint32_t ord_key(float f) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Per-field minimum and maximum of the stored (decoded) attribute values:
+// Per-field minimum and maximum of the stored (decoded) values, F - I for a
+// REL_IDENTITY F:
 // rng[f] = min key, rng[4 + f] = max key (ord_key order).
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ sch, const uint32_t *__restrict__ words,
@@ -509,6 +510,10 @@ __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ 
         dec_field<DIM, 1, float>(&s->f[1], words, cap, p4, v);
         dec_field<DIM, 2, float>(&s->f[2], words, cap, p4, C);
         dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+        if (s->f[3].rel) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) F[a * (DIM + 1)] -= 1.0f;
+        }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             const uint32_t kx = ord_key((float)xd[a]), kv = ord_key(v[a]);

@@ -124,8 +124,12 @@ def test_adjoint_trajectory_vs_oracle(gpu_lib, orc, dim, T, kind, K):
     assert_weighted_close(res["G"], G, steps, 2e-2, "G")
     # Alg. 1 ranges: min / max of the stored values over s_0..s_T
     stack = np.stack(states)
+    rel_f = any(fs["field"] == "F" and fs.get("rel_identity") for fs in scene["scheme"]["fields"])
     for f, sl in field_slices(dim).items():
-        vals = stack[:, sl, :]
+        vals = stack[:, sl, :].copy()
+        if f == "F" and rel_f:
+            for a in range(dim):
+                vals[:, a * (dim + 1), :] -= 1.0
         span = float(vals.max() - vals.min()) + 1e-12
         assert abs(res["lo"][f] - float(vals.min())) <= 1e-3 * span, f
         assert abs(res["hi"][f] - float(vals.max())) <= 1e-3 * span, f
@@ -283,3 +287,49 @@ def test_adjoint_c5_full(gpu_lib, orc):
     # a uniform shift of every position at any step moves the centre of
     # mass by the same amount (quadratic B-splines reproduce affine fields)
     assert abs(a["G"]["x"] - 65.0) <= 0.05 * 65.0, a["G"]["x"]
+
+
+def full_precision_scheme(dim, seed=0):
+    """Every field as raw float32 (F stored as F - I, like the quantized
+    schemes), the full-precision run of Alg. 1."""
+    return {"dim": dim, "seed": seed, "fields": [WL.raw("x"), WL.raw("v"), WL.raw("C"), WL.raw("F", rel_identity=True)]}
+
+
+def test_alg1_error_bounded_scheme(gpu_lib):
+    """Alg. 1 end to end: gradients and ranges from a full-precision run,
+    bits from the error-bounded solver (Eq. 10), then the quantized run's
+    objective stays within the requested relative error."""
+    note("Alg. 1 error-bounded on the adjoint scene (16^3, 16 steps)")
+    scene = WL.c5(seed=8, grid_res=16)
+    T, eps = 16, 1e-3
+    fp = WL.with_scheme(scene, full_precision_scheme(3, 8))
+    ctx = gpu_context(gpu_lib, fp)
+    ref = ctx.adjoint(T, objective="ke", checkpoint_every=4)
+    ctx.close()
+    base = WL.scheme_c1(3, False, 8)
+    scheme, sol = gpu_lib.auto_scheme(base, ref, scene["n"], mode="error", eps=eps, min_bits=4)
+    print(f"[alg1] z={ref['z']:.6e} bits={sol['bits']} g={ref['g']}", flush=True)
+    assert sol["expected_error"] <= (eps * ref["z"]) ** 2
+    q = gpu_context(gpu_lib, WL.with_scheme(scene, scheme))
+    zq = q.adjoint(T, objective="ke", checkpoint_every=4)["z"]
+    q.close()
+    assert abs(zq - ref["z"]) <= 3.0 * eps * abs(ref["z"]), (zq, ref["z"])
+
+
+def test_alg1_memory_bounded_scheme(gpu_lib):
+    note("Alg. 1 memory-bounded on the adjoint scene (16^3, 16 steps)")
+    scene = WL.c5(seed=9, grid_res=16)
+    T = 16
+    fp = WL.with_scheme(scene, full_precision_scheme(3, 9))
+    ctx = gpu_context(gpu_lib, fp)
+    ref = ctx.adjoint(T, objective="ke", checkpoint_every=0)
+    ctx.close()
+    scheme, sol = gpu_lib.auto_scheme(WL.scheme_c1(3, True, 9), ref, scene["n"], mode="memory", eps=0.5, min_bits=4)
+    n = scene["n"]
+    assert sol["total_bits"] <= 0.5 * 32 * n * (3 + 3 + 9 + 9)
+    sizes = gpu_lib.mpmq_query_sizes(scheme, scene["params"], n)
+    assert sizes["record_bits"] == sum(f["bits"] * (3 if f["field"] in "xv" else 9) for f in scheme["fields"])
+    q = gpu_context(gpu_lib, WL.with_scheme(scene, scheme))
+    zq = q.adjoint(T, objective="ke", checkpoint_every=0)["z"]
+    q.close()
+    assert math.isfinite(zq) and abs(zq - ref["z"]) <= 0.05 * abs(ref["z"]), (zq, ref["z"])
