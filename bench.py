@@ -3,7 +3,7 @@
 Metric: particle-substeps/s and bytes/particle, quantized vs the float32
 layout, for the 3D elastic workload of 3e8 particles (186 cubes of 60^3
 cells in a 512^3 grid, dt = 1e-4; x 3x21-bit fixed, v 3x13-bit
-shared-exponent, C 9x16-bit, F 9x14-bit, all dithered: 48 B per particle
+shared-exponent, C 9x16-bit shared-exponent, F 9x14-bit, all dithered: 48 B per particle
 against 96 B for float32).  A step is one full substep of the hot path
 (P2G, grid update, G2P, dithered re-encode and store), with the packed
 state resident in HBM; the particle sort runs once at set-up (during the
@@ -87,7 +87,8 @@ def build_scene(config, device):
             if i % 40 == 0:
                 log(f"generated cube {i}/{len(lay['counts'])} ({time.time() - t0:.1f}s)")
         desc = ("3D MLS-MPM elastic, 300M particles in 186 cubes of 60^3 cells, 512^3 grid, dt=1e-4, "
-                "fixed-corotated E=1e3 nu=0.2; x 3x21b fixed, v 3x13b shared-exp (6b), C 9x16b, F 9x14b, dithered")
+                "fixed-corotated E=100 nu=0.2; x 3x21b fixed, v 3x13b shared-exp (6b), C 9x16b shared-exp (6b), "
+                "F 9x14b fixed (F-I), dithered")
         scene = {"name": "c3", "scheme": scheme, "params": params, "n": n, "desc": desc, "grid": 512,
                  "steps_cfg": 10}
     else:

@@ -34,7 +34,7 @@ def test_query_sizes_record_widths():
     assert mq.mpmq_query_sizes(c1["scheme"], c1["params"], 8192)["words_per_particle"] == 7
     p3 = WL.c3_params()
     s3 = mq.mpmq_query_sizes(WL.scheme_c3(), p3, 300_000_000)
-    assert s3["words_per_particle"] == 12 and s3["record_bits"] == 378
+    assert s3["words_per_particle"] == 12 and s3["record_bits"] == 384
     assert s3["packed_bytes"] == 48 * 300_000_000
     f3 = mq.mpmq_query_sizes(WL.scheme_fp32(3), p3, 300_000_000)
     assert f3["packed_bytes"] == 96 * 300_000_000

@@ -216,7 +216,7 @@ def test_rollout_autograd(gpu_lib):
     ref = ref_ctx.adjoint(5, objective="ke", checkpoint_every=2, want_lambda0=True)
     lam = ref["lambda0"].cpu().numpy().astype(np.float64)
     grads = np.concatenate([t.grad.cpu().numpy().astype(np.float64) for t in ts], axis=0)
-    assert math.isclose(float(z), ref["z"], rel_tol=1e-12)
+    assert math.isclose(float(z.detach()), ref["z"], rel_tol=1e-12)
     steps = field_steps(scene["scheme"])
     assert_weighted_close(split_lambda(grads, 3), split_lambda(lam, 3), steps, 1e-4, "autograd")
     ctx.close()
@@ -298,7 +298,11 @@ def full_precision_scheme(dim, seed=0):
 def test_alg1_error_bounded_scheme(gpu_lib):
     """Alg. 1 end to end: gradients and ranges from a full-precision run,
     bits from the error-bounded solver (Eq. 10), then the quantized run's
-    objective stays within the requested relative error."""
+    objective stays within the requested relative error.  The scheme is
+    dithered (Sec. 5): its rounding errors are unbiased and independent
+    between steps as the error model of Eq. 8 assumes, with variance
+    Delta^2 / 6 instead of Delta^2 / 12, so the RMS error bound is
+    sqrt(2) eps z."""
     note("Alg. 1 error-bounded on the adjoint scene (16^3, 16 steps)")
     scene = WL.c5(seed=8, grid_res=16)
     T, eps = 16, 1e-3
@@ -306,14 +310,19 @@ def test_alg1_error_bounded_scheme(gpu_lib):
     ctx = gpu_context(gpu_lib, fp)
     ref = ctx.adjoint(T, objective="ke", checkpoint_every=4)
     ctx.close()
-    base = WL.scheme_c1(3, False, 8)
+    base = WL.scheme_c1(3, True, 8)
     scheme, sol = gpu_lib.auto_scheme(base, ref, scene["n"], mode="error", eps=eps, min_bits=4)
     print(f"[alg1] z={ref['z']:.6e} bits={sol['bits']} g={ref['g']}", flush=True)
     assert sol["expected_error"] <= (eps * ref["z"]) ** 2
-    q = gpu_context(gpu_lib, WL.with_scheme(scene, scheme))
-    zq = q.adjoint(T, objective="ke", checkpoint_every=4)["z"]
-    q.close()
-    assert abs(zq - ref["z"]) <= 3.0 * eps * abs(ref["z"]), (zq, ref["z"])
+    errs = []
+    for seed in range(3):
+        scheme["seed"] = 100 + seed
+        q = gpu_context(gpu_lib, WL.with_scheme(scene, scheme))
+        errs.append(q.adjoint(T, objective="ke", checkpoint_every=4)["z"] - ref["z"])
+        q.close()
+    rms = math.sqrt(sum(e * e for e in errs) / len(errs))
+    print(f"[alg1] errors {errs} rms/z {rms / ref['z']:.3e} (eps {eps})", flush=True)
+    assert rms <= 3.0 * math.sqrt(2.0) * eps * abs(ref["z"]), (errs, ref["z"])
 
 
 def test_alg1_memory_bounded_scheme(gpu_lib):

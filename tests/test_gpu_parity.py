@@ -177,7 +177,9 @@ def test_grid_mass_conservation(gpu_lib, dim):
     g = (ctx.grid_a if s % 2 == 0 else ctx.grid_b).view(torch.int64).view(-1, 4)
     mass = g[:, 3].sum().item() * 2.0 ** -32 * m_p
     mom = [g[:, a].sum().item() * 2.0 ** -32 * m_p for a in range(dim)]
-    assert abs(mass - m_p * sc["n"]) <= 1e-9 * m_p * sc["n"]
+    # the weights of one particle sum to 1 up to FP32 rounding of the
+    # B-spline products (a few ulp of 2^-24 each), plus 2^-33 per node
+    assert abs(mass - m_p * sc["n"]) <= 1e-6 * m_p * sc["n"]
     # P2G conserves momentum: sum over nodes = sum over particles of m v (decoded state)
     _, gv, _, _ = gpu_decode_np(ctx)
     for a in range(dim):
@@ -227,6 +229,6 @@ def test_step_before_encode_is_state_error(gpu_lib):
         ctx.step(1)
     assert e.value.status == -4
     with pytest.raises(gpu_lib.MpmqError) as e:
-        ctx.adjoint()
-    assert e.value.status == -5
+        ctx.adjoint(1)
+    assert e.value.status == -4
     ctx.close()

@@ -99,7 +99,7 @@ def test_config_record_sizes(orc):
     assert orc.layout(WL.scheme_c1(2))[3] == 7       # 200 bits
     assert orc.layout(WL.scheme_c1(3, True))[3] == 13  # 396 bits
     _, _, total, W = orc.layout(WL.scheme_c3())
-    assert total == 378 and W == 12                   # 48 B vs 96 B
+    assert total == 384 and W == 12                   # 48 B vs 96 B
 
 
 def test_invalid_schemes_rejected(orc):

@@ -17,8 +17,9 @@ Table "large_scale"):
   c3  3D, 3e8 particles in 186 cubes of 60^3 cells, each centred in its own
       64^3 slot of the 8^3 slot lattice of a 512^3 grid (30% filled),
       dt=1e-4, 10 steps; x 3x21-bit fixed, v 3x13-bit shared-exponent float
-      (6-bit exponent), F 9x14-bit fixed (F-I), C 9x16-bit fixed, all
-      dithered: 378 bits = 12 words = 48 B per particle.
+      (6-bit exponent), F 9x14-bit fixed (F-I), C 9x16-bit shared-exponent
+      float (6-bit exponent, |C| < 2048), all dithered: 384 bits = 12 words
+      = 48 B per particle; E=100 (see c3_params).
   c5  3D adjoint scene: one cube of side 0.5 (8 particles per cell, so
       grid_res^3 particles: 262144 at 64^3), corner (0.25, 0.25, 0.25),
       velocity = one U(-1,1)^3 drift + a rigid spin with angular velocity
@@ -65,7 +66,7 @@ def scheme_c3(seed=0):
     return {"dim": 3, "seed": seed, "fields": [
         fixed("x", 21, 0.0, 1.0, True),
         shared_exp("v", 13, 6, 20.0, True),
-        fixed("C", 16, -50.0, 50.0, True),
+        shared_exp("C", 16, 6, 2048.0, True),
         fixed("F", 14, -1.0, 1.0, True, rel_identity=True)]}
 
 
