@@ -171,23 +171,24 @@ def cpu_baseline(scene):
     import workloads as WL
     if scene["name"] == "c3":
         sub = WL.c3(only=[0])
-        sample = (f"cube 0 of 186 ({sub['n']} particles) on the full 512^3 grid, 1 substep after a "
+        sample = (f"cube 0 of 186 ({sub['n']} particles) on the full 512^3 grid, 3 substeps after a "
                   f"warm-up substep that includes the sort")
     elif scene["name"] == "c2":
         sub = WL.c2(cubes=1)
-        sample = f"cube 0 of 4 ({sub['n']} particles) on the 128^3 grid, 1 substep after a warm-up substep"
+        sample = f"cube 0 of 4 ({sub['n']} particles) on the 128^3 grid, 3 substeps after a warm-up substep"
     else:
         sub = WL.c1()
-        sample = "the full scene (8192 particles), 1 substep after a warm-up substep"
+        sample = "the full scene (8192 particles), 3 substeps after a warm-up substep"
     x, v, C, F = sub["state"]
     words, _ = oracle.encode(sub["scheme"], x, v, C, F, 0, 2)
     sim = oracle.Sim(sub["scheme"], sub["params"], words)
     sim.step(1)
+    reps = 3
     t0 = time.perf_counter()
-    sim.step(1)
+    sim.step(reps)
     dt = time.perf_counter() - t0
     sim.close()
-    return {"value": sub["n"] / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+    return {"value": reps * sub["n"] / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
             "sample": sample, "seconds": round(dt, 3)}
 
 

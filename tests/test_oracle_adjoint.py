@@ -105,3 +105,27 @@ def test_objective_gradients(orc):
     m = p["rho"] * p["p_vol"]
     assert np.isclose(z, 0.5 * m * (st[1] ** 2).sum())
     assert np.allclose(lam[3:6], m * st[1])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_centre_of_mass_invariants(orc, dim):
+    """Away from the walls a uniform shift of every stored position moves the
+    centre of mass by the same amount (quadratic B-splines reproduce affine
+    velocity fields), and internal forces and the affine term conserve
+    momentum, so C and F do not move it: G_x = T + 1 along the axis, 0 across
+    it, and G_C = G_F = 0 up to round-off."""
+    p, st = scene(dim, 40 + dim, n=50)
+    s0 = orc.pack_state(*st)
+    T = 6
+    states = trajectory(orc, p, s0, T)
+    rows = orc.field_rows(dim)
+    for axis in range(dim):
+        z, G, g, A, lam0 = orc.adjoint_full(p, states, "com", axis)
+        assert abs(G["x"] - (T + 1)) <= 1e-9 * (T + 1), G["x"]
+        # per axis: sum over the particles of lambda_x along `axis` is 1 at every step
+        assert abs(lam0[axis].sum() - 1.0) <= 1e-9
+        for b in range(dim):
+            if b != axis:
+                assert abs(lam0[b].sum()) <= 1e-9
+        for f in ("C", "F"):
+            assert abs(G[f]) <= 1e-9 * A["x"], (f, G[f])
