@@ -346,10 +346,17 @@ int orc_sort_order(const orc_params *p, int64_t n, const double *x, int64_t *ord
         double fx[3], w[3][3];
         stencil(p, xp, base, fx, w);
         int64_t cell_lin = node_index(p, base);
-        int64_t blk = 0, cib = 0;
-        for (int a = dim - 1; a >= 0; --a) {
-            blk = blk * nb + base[a] / B;
-            cib = cib * B + base[a] % B;
+        int64_t blk = 0;
+        for (int a = dim - 1; a >= 0; --a) blk = blk * nb + base[a] / B;
+        /* cell within the block, in tiles of 64 cells (4x4x4 in 3D, 8x8 in
+         * 2D) taken in x-fastest order, cells x-fastest inside a tile */
+        int64_t cib;
+        if (dim == 3) {
+            int cx = base[0] % B, cy = base[1] % B, cz = base[2] % B;
+            cib = (((cz / 4) * 2 + cy / 4) * 2 + cx / 4) * 64 + ((cz % 4) * 4 + cy % 4) * 4 + cx % 4;
+        } else {
+            int cx = base[0] % B, cy = base[1] % B;
+            cib = ((cy / 8) * 2 + cx / 8) * 64 + (cy % 8) * 8 + cx % 8;
         }
         keys[q].block = blk;
         keys[q].rank = count[cell_lin]++;

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(WG) void k_encode(const DevScheme *__restrict__ sch
             Cv[c] = C[c * n + p];
             Fv[c] = F[c * n + p];
         }
-        const Draws rnd = dither_draws(scheme_ref(sch), (uint32_t)p, step, tag);
+        Draws rnd;
+        rnd.init(scheme_ref(sch), (uint32_t)p, step, tag);
         OutStream os{words, cap, (uint32_t)p * 4u, 0ull, 0, 0};
         encode_record<DIM, true>(sch, xv, vv, Cv, Fv, rnd, os, ls, qx, qv, qC, qF);
         if (ids) ids[p] = (uint32_t)p;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(WG) void k_decode(const DevScheme *__restrict__ sch
 
 // ---------------------------------------------------------------------------
 // particle sort by cell
-// key = block * BLK^dim + cell-in-block of the (clamped) base cell
+// key = block * BLK^dim + cell-in-block of the (clamped) base cell (tiled)
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_sort_keys(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
@@ -147,11 +148,19 @@ __global__ __launch_bounds__(WG) void k_sort_keys(const DevScheme *__restrict__ 
     int base[DIM];
     float fx[DIM];
     stencil_base<DIM>(xv, P.inv_dx_d, P.res, base, fx);
-    uint32_t blk = 0, cib = 0;
+    uint32_t blk = 0;
 #pragma unroll
-    for (int a = DIM - 1; a >= 0; --a) {
-        blk = blk * (uint32_t)P.nb + (uint32_t)(base[a] >> L);
-        cib = cib * B + (uint32_t)(base[a] & (B - 1));
+    for (int a = DIM - 1; a >= 0; --a) blk = blk * (uint32_t)P.nb + (uint32_t)(base[a] >> L);
+    // cell within the block in tiles of 64 cells (4x4x4 / 8x8), so that the
+    // 64 lanes of a wave hold a compact tile: its LDS node addresses then
+    // fall in distinct banks for the G2P reads and the P2G atomics
+    uint32_t cib;
+    if constexpr (DIM == 3) {
+        const uint32_t cx = base[0] & 7, cy = base[1] & 7, cz = base[2] & 7;
+        cib = ((((cz >> 2) * 2 + (cy >> 2)) * 2 + (cx >> 2)) << 6) + (((cz & 3) * 4 + (cy & 3)) << 2) + (cx & 3);
+    } else {
+        const uint32_t cx = base[0] & 15, cy = base[1] & 15;
+        cib = ((((cy >> 3) * 2) + (cx >> 3)) << 6) + ((cy & 7) << 3) + (cx & 7);
     }
     const uint32_t key = blk * (uint32_t)Geo<DIM>::CPB + cib;
     keys[p] = key;
@@ -482,41 +491,52 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
     }
     if (in_tile) {
         const int l0 = (DIM == 3) ? (l[DIM - 1] * TB + l[1]) * TB + l[0] : l[1] * TB + l[0];
+        // node values stepped along each axis (q + sum_b a_b o_b by additions)
         if constexpr (DIM == 3) {
+            double vz[3] = {q[0], q[1], q[2]};
 #pragma unroll
             for (int oz = 0; oz < 3; ++oz) {
-                double vz[3];
+                if (oz > 0)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) vz[a] = q[a] + ac[2][a] * (double)oz;
+                    for (int a = 0; a < 3; ++a) vz[a] += ac[2][a];
+                double vzy[3] = {vz[0], vz[1], vz[2]};
 #pragma unroll
                 for (int oy = 0; oy < 3; ++oy) {
-                    const double wzy = w[2][oz] * w[1][oy];
-                    double vzy[3];
+                    if (oy > 0)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) vzy[a] = vz[a] + ac[1][a] * (double)oy;
+                        for (int a = 0; a < 3; ++a) vzy[a] += ac[1][a];
+                    const double wzy = w[2][oz] * w[1][oy];
+                    double val[3] = {vzy[0], vzy[1], vzy[2]};
 #pragma unroll
                     for (int ox = 0; ox < 3; ++ox) {
+                        if (ox > 0)
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) val[a] += ac[0][a];
                         const double wt = wzy * w[0][ox];
                         const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a)
-                            atomicAdd(&acc[a * TN + idx], fixp(wt, vzy[a] + ac[0][a] * (double)ox));
+                        for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
                         atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
                     }
                 }
             }
         } else {
+            double vy[2] = {q[0], q[1]};
 #pragma unroll
             for (int oy = 0; oy < 3; ++oy) {
-                double vy[2];
+                if (oy > 0)
 #pragma unroll
-                for (int a = 0; a < 2; ++a) vy[a] = q[a] + ac[1][a] * (double)oy;
+                    for (int a = 0; a < 2; ++a) vy[a] += ac[1][a];
+                double val[2] = {vy[0], vy[1]};
 #pragma unroll
                 for (int ox = 0; ox < 3; ++ox) {
+                    if (ox > 0)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) val[a] += ac[0][a];
                     const double wt = w[1][oy] * w[0][ox];
                     const int idx = l0 + oy * TB + ox;
 #pragma unroll
-                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, vy[a] + ac[0][a] * (double)ox));
+                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
                     atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
                 }
             }
@@ -882,7 +902,8 @@ __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__
                     Fn[i * DIM + j] = t;
                 }
             // dithered encode (Eq. 11), streamed in place in placement order
-            const Draws rnd = dither_draws(sp, (uint32_t)p, step, 1u);
+            Draws rnd;
+            rnd.init(sp, (uint32_t)p, step, 1u);
             OutStream os{words, cap, p4, 0ull, 0, 0};
             double qx[DIM];
             float qv[DIM], qC[D2], qF[D2];

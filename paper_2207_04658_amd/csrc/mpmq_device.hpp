@@ -110,28 +110,37 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+// Dither draws, generated on demand one Philox group (8 components) at a
+// time.  A field's components are consecutive canonical indices, so they
+// span at most two groups: two cached groups (by group parity) serve every
+// field without regenerating.  The group tags are wave-uniform.
 struct Draws {
-    uint32_t r[12];
+    uint32_t r[2][4];
+    int tag[2];
+    uint32_t slot, step, ptag, seed_lo, seed_hi;
+    __device__ __forceinline__ void init(SchemeRef s, uint32_t slot_, uint32_t step_, uint32_t tag_) {
+        tag[0] = tag[1] = -1;
+        slot = slot_;
+        step = step_;
+        ptag = tag_;
+        seed_lo = s->seed_lo;
+        seed_hi = s->seed_hi;
+    }
+    // 16-bit draw of canonical component k (k is a compile-time index)
+    __device__ __forceinline__ uint32_t draw16(int k) {
+        const int g = k >> 3, b = g & 1;
+        if (tag[b] != g) {
+            philox10(slot, step, (uint32_t)g, ptag, seed_lo, seed_hi, r[b]);
+            tag[b] = g;
+        }
+        const uint32_t w = r[b][(k >> 1) & 3];
+        return (k & 1) ? (w >> 16) : (w & 0xffffu);
+    }
 };
 
-__device__ __forceinline__ Draws dither_draws(SchemeRef s, uint32_t slot, uint32_t step, uint32_t tag) {
-    Draws d;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        if ((s->dither_groups >> j) & 1u) {
-            philox10(slot, step, (uint32_t)j, tag, s->seed_lo, s->seed_hi, &d.r[4 * j]);
-        } else {
-            d.r[4 * j] = d.r[4 * j + 1] = d.r[4 * j + 2] = d.r[4 * j + 3] = 0u;
-        }
-    }
-    return d;
-}
-
-// xi' in (0,1): (r16 + 1/2) 2^-16, exact in binary64; k is a compile-time index.
-__device__ __forceinline__ double dither_xi(const Draws &d, int k) {
-    const uint32_t w = d.r[k >> 1];
-    const uint32_t h = (k & 1) ? (w >> 16) : (w & 0xffffu);
-    return ((double)h + 0.5) * (1.0 / 65536.0);
+// xi' in (0,1): (r16 + 1/2) 2^-16, exact in binary64.
+__device__ __forceinline__ double dither_xi(Draws &d, int k) {
+    return ((double)d.draw16(k) + 0.5) * (1.0 / 65536.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,7 +184,7 @@ __device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, doub
 // Shared-exponent vector: E from the largest magnitude, raised by one if a
 // magnitude rounds up to 2^(m-1); stored as E - E_min, then sign|magnitude.
 template <int DIM, int FID, typename T, bool RS>
-__device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, const Draws &rnd, OutStream &os,
+__device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &rnd, OutStream &os,
                                          LaneStats &ls, T *qv) {
 #pragma clang fp contract(off)
     constexpr int NC = ncomp<DIM, FID>(), K0 = canon0<DIM, FID>();
@@ -234,7 +243,7 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, const D
 // returns the decoded stored values in qv (Eq. 1: the next substep starts
 // from these).  T is double for x and float for v, C, F.
 template <int DIM, int FID, typename T, bool RS>
-__device__ __forceinline__ void enc_field(const FieldRef f, const T *val, const Draws &rnd, OutStream &os,
+__device__ __forceinline__ void enc_field(const FieldRef f, const T *val, Draws &rnd, OutStream &os,
                                           LaneStats &ls, T *qv) {
 #pragma clang fp contract(off)
     constexpr int NC = ncomp<DIM, FID>(), K0 = canon0<DIM, FID>();
@@ -299,7 +308,7 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
 // Encodes all four fields in placement order; qx.. receive the stored values.
 template <int DIM, bool RS>
 __device__ __forceinline__ void encode_record(const DevScheme *sp, const double *x, const float *v,
-                                              const float *C, const float *F, const Draws &rnd, OutStream &os,
+                                              const float *C, const float *F, Draws &rnd, OutStream &os,
                                               LaneStats &ls, double *qx, float *qv, float *qC, float *qF) {
 #pragma unroll 1
     for (int slot = 0; slot < 4; ++slot) {
@@ -393,7 +402,8 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
                     c22 = R[0] * R[4] - R[1] * R[3];
         const float det = R[0] * c00 + R[1] * c01 + R[2] * c02;
         const bool ok = fabsf(det) > 1e-20f;
-        const float hid = ok ? 0.5f / det : 0.0f;
+        // hardware reciprocal (1 ulp): the iteration absorbs its error
+        const float hid = ok ? 0.5f * __builtin_amdgcn_rcpf(det) : 0.0f;
         float Rn[9] = {0.5f * R[0] + hid * c00, 0.5f * R[1] + hid * c01, 0.5f * R[2] + hid * c02,
                        0.5f * R[3] + hid * c10, 0.5f * R[4] + hid * c11, 0.5f * R[5] + hid * c12,
                        0.5f * R[6] + hid * c20, 0.5f * R[7] + hid * c21, 0.5f * R[8] + hid * c22};

@@ -287,8 +287,18 @@ def test_sort_order_properties(orc):
         cell = np.zeros(n, dtype=np.int64)
         for a in reversed(range(dim)):
             blk = blk * nb + base[a] // B
-            cib = cib * B + base[a] % B
             cell = cell * res + base[a]
+        # cell within the block: tiles of 64 cells (4x4x4 / 8x8), tile-major,
+        # both levels x-fastest
+        T = 4 if dim == 3 else 8
+        c = base % B
+        tile = np.zeros(n, dtype=np.int64)
+        inner = np.zeros(n, dtype=np.int64)
+        for a in reversed(range(dim)):
+            tile = tile * (B // T) + c[a] // T
+            inner = inner * T + c[a] % T
+        cib = tile * 64 + inner
+        assert np.array_equal(np.sort(np.unique(cib)), np.unique(cib)) and cib.max() < B ** dim
         # rank of each particle among earlier slots of its cell
         rank = np.zeros(n, dtype=np.int64)
         seen = {}

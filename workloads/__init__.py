@@ -25,6 +25,13 @@ Table "large_scale"):
       velocity = one U(-1,1)^3 drift + a rigid spin with angular velocity
       U(-2,2)^3 about the cube centre + per-particle U(-0.1,0.1) noise;
       dt=2e-4, 64 steps, the c2 scheme, no re-sort.
+  c4  serving stream: 256 scenes arriving as a Poisson process; per scene
+      (seeded by its index) 2D or 3D with equal odds, a grid resolution from
+      {32, 64, 128, 256} (per axis), a particle count log-uniform in
+      [4096, 2^21] placed uniformly in a box of half the domain's side
+      centred at (0.5, 0.6, 0.5), one velocity from U(-1,1)^d, a random
+      scheme (12-24 bits per field, random kinds, dither and placement
+      order), dt = 0.25 dx / c with c the P-wave speed, 100 steps.
   fp32 layout: the same scene with every field stored as raw float32.
 """
 from __future__ import annotations
@@ -173,6 +180,47 @@ def c5(seed=0, grid_res=64, steps=64):
     return {"name": "c5", "scheme": sc, "steps": steps, "n": n,
             "params": params(3, grid_res, 2e-4, side ** 3 / n, sort_every=0),
             "state": (x, v, C, F)}
+
+
+def c4_scene(stream_seed, index, steps=100, n_max=2 ** 21, materialize=True):
+    """Scene `index` of the serving stream (see module docstring).  With
+    materialize=False the state is described by "x" (float32 [dim, n]) and
+    "vel" (one velocity for every particle; C = 0, F = I) and "state" is
+    None; c4_state() builds the arrays."""
+    rng = np.random.default_rng([stream_seed, 4, index])
+    dim = int(rng.choice([2, 3]))
+    res = int(rng.choice([32, 64, 128, 256]))
+    n = int(round(math.exp(rng.uniform(math.log(4096), math.log(n_max)))))
+    side = 0.5
+    corner = np.array([0.25, 0.35, 0.25])[:dim]
+    x = rng.random((dim, n), dtype=np.float32)
+    x *= np.float32(side)
+    x += corner.astype(np.float32)[:, None]
+    vel = rng.uniform(-1.0, 1.0, dim).astype(np.float32)
+    mu = E_MODULUS / (2 * (1 + POISSON))
+    la = E_MODULUS * POISSON / ((1 + POISSON) * (1 - 2 * POISSON))
+    c = math.sqrt((la + 2 * mu) / DENSITY)
+    dt = 0.25 / (res * c)
+    scheme = random_scheme(rng, dim, seed=int(rng.integers(0, 2 ** 63)))
+    sc = {"name": f"c4-{index}", "index": index, "scheme": scheme, "steps": steps, "n": n,
+          "params": params(dim, res, dt, side ** dim / n), "x": x, "vel": vel, "state": None}
+    if materialize:
+        sc["state"] = c4_state(sc)
+    return sc
+
+
+def c4_state(sc):
+    x = sc["x"]
+    dim, n = x.shape
+    v = np.repeat(sc["vel"][:, None], n, axis=1)
+    _, C, F = rest_state(dim, n)
+    return (x, v, C, F)
+
+
+def c4_arrivals(stream_seed, count=256, rate=100.0):
+    """Poisson arrival times (seconds) of the serving stream."""
+    rng = np.random.default_rng([stream_seed, 44])
+    return np.cumsum(rng.exponential(1.0 / rate, count))
 
 
 C3_TOTAL = 300_000_000
