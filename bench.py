@@ -109,10 +109,16 @@ def build_scene(config, device):
     return scene, (x, v, C, F)
 
 
-def run_layout(mq, scene, scheme, state, steps, warmup, label):
+def run_layout(mq, scene, scheme, state, steps, warmup, label, specialize=True):
     import torch
     n = scene["n"]
     ctx = mq.Context(scheme, scene["params"], n, track_ids=False)
+    jit_s = 0.0
+    if specialize:
+        t0 = time.perf_counter()
+        ctx.specialize(True)
+        jit_s = time.perf_counter() - t0
+        log(f"{label}: scheme-specialized kernels ready in {jit_s:.2f} s")
     sz = ctx.sizes
     log(f"{label}: W={sz['words_per_particle']} words, state {sz['packed_bytes'] / 1e9:.2f} GB, "
         f"scratch {sz['scratch_bytes'] / 1e9:.2f} GB, grid 2x{sz['grid_bytes'] / 1e9:.2f} GB")
@@ -142,7 +148,7 @@ def run_layout(mq, scene, scheme, state, steps, warmup, label):
         ", ".join(f"{k}={v[1] / max(v[0], 1):.3f}ms" for k, v in kt.items()))
     return {"ms_per_step": per_step, "value": n * steps / (ms / 1e3) if ms > 0 else 0.0,
             "kernels": {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()},
-            "sort_ms": sort_ms, "stats": st, "W": sz["words_per_particle"],
+            "sort_ms": sort_ms, "stats": st, "W": sz["words_per_particle"], "specialize_s": jit_s,
             "bytes_per_particle": 4 * sz["words_per_particle"],
             "footprint_bytes": sz["packed_bytes"] + 2 * sz["grid_bytes"] + sz["scratch_bytes"]}
 
@@ -203,20 +209,106 @@ def calib_copy():
     print(json.dumps({"calib_copy_bytes": nbytes}))
 
 
+def bench_serving(a):
+    """Serving stream: throughput over the makespan and latency percentiles."""
+    import numpy as np
+    import workloads as WL
+    from paper_2207_04658_amd.serving import Server
+    t0 = time.time()
+    scenes = [WL.c4_scene(0, i, materialize=False) for i in range(a.scenes)]
+    arrivals = WL.c4_arrivals(0, a.scenes, a.rate)
+    log(f"generated {a.scenes} scenes ({sum(s['n'] for s in scenes)} particles) in {time.time() - t0:.1f}s")
+    warm = Server(streams=2, steps_per_tick=10).run(scenes[:2])  # loads the kernels
+    log(f"warm-up: {len(warm.latencies_s)} scenes")
+    res = Server(hbm_budget_bytes=200e9, streams=8, steps_per_tick=10).run(scenes, arrivals)
+    lat = np.array(list(res.latencies_s.values()))
+    line = {
+        "metric": "serving throughput (particle-substeps/s) with per-scene latency",
+        "value": round(res.throughput(), 1), "unit": "particle-substeps/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{a.scenes} MLS-MPM scenes (2D/3D), Poisson arrivals at {a.rate}/s, "
+                               "particles log-uniform 4096-2^21, grids 32-256 per axis, 100 steps each, "
+                               "random 12-24-bit schemes, 200 GB HBM budget"},
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                      "max": round(float(lat.max()), 4)},
+        "makespan_s": round(res.makespan_s, 4), "particle_substeps": res.particle_substeps,
+        "max_active_scenes": res.max_active, "peak_hbm_bytes": res.peak_bytes,
+        "queue_wait_s_max": round(max(res.queue_wait_s.values()), 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_adjoint(a):
+    """Adjoint scene at full size: forward + backward of 64 substeps."""
+    import torch
+    import numpy as np
+    import oracle
+    import workloads as WL
+    import paper_2207_04658_amd as mq
+    sc = WL.c5(seed=0)
+    T = sc["steps"]
+    res = {}
+    for K in (8, 0):
+        ctx = mq.Context(sc["scheme"], sc["params"], sc["n"])
+        ts = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in sc["state"]]
+        ctx.encode(*ts)
+        ctx.adjoint(2, objective="ke", checkpoint_every=K)  # warm-up
+        ms = []
+        for _ in range(3):
+            ctx.encode(*ts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.adjoint(T, objective="ke", checkpoint_every=K)
+            ms.append((time.perf_counter() - t0) * 1e3)
+        res[K] = (min(ms), r)
+        log(f"adjoint K={K}: {min(ms):.1f} ms, recomputed {r['recomputed']}, states {r['states']}")
+        ctx.close()
+    # oracle: the FP64 adjoint of one substep on the same scene at 16^3 (4096 particles)
+    small = WL.c5(seed=0, grid_res=16)
+    x, v, C, F = small["state"]
+    s0 = oracle.pack_state(*(np.asarray(t, dtype=np.float64) for t in (x, v, C, F)))
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 5.0:
+        oracle.step_vjp(small["params"], s0, s0)
+        reps += 1
+    cpu_rate = reps * small["n"] / (time.perf_counter() - t0)
+    n = sc["n"]
+    ms8, r8 = res[8]
+    line = {
+        "metric": "adjoint particle-substeps/s (forward + backward through the quantized substep)",
+        "value": round(n * T / (ms8 / 1e3), 1), "unit": "particle-substeps/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D elastic cube, 262144 particles, 64^3 grid, 64 steps, checkpoint every 8, "
+                               "kinetic-energy objective, c2 scheme"},
+        "ms": {"checkpoint_every_8": round(ms8, 2), "bisection": round(res[0][0], 2)},
+        "states_held": {"checkpoint_every_8": r8["states"], "bisection": res[0][1]["states"]},
+        "recomputed_substeps": {"checkpoint_every_8": r8["recomputed"], "bisection": res[0][1]["recomputed"]},
+        "g": r8["g"],
+        "cpu_baseline": {"value": round(cpu_rate, 1), "unit": "particle-substeps/s (backward only)", "cores": 1,
+                         "kind": "oracle", "sample": "orc_step_vjp on the 16^3 version of the scene (4096 particles)"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--scenes", type=int, default=256, help="c4: scenes in the stream")
+    ap.add_argument("--rate", type=float, default=200.0, help="c4: Poisson arrival rate (scenes/s)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["quant", "fp32"], default=None)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--generic", action="store_true", help="run the generic (run-time scheme) kernels")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one MI355X: this build has no multi-GPU path (the design for "
-              "sharding by spatial slabs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one MI355X: the library has no multi-GPU path (it would shard the grid "
+              "by spatial slabs and exchange the node shells of shared faces); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     if a.calib_copy:
         calib_copy()
@@ -227,15 +319,20 @@ def main():
     mq.load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.config == "c4":
+        return bench_serving(a)
+    if a.config == "c5":
+        return bench_adjoint(a)
     scene, state = build_scene(a.config, dev)
     n = scene["n"]
     log(f"scene {scene['name']}: {n} particles")
     out = {}
     if a.only in (None, "quant"):
-        out["quant"] = run_layout(mq, scene, scene["scheme"], state, a.steps, a.warmup, "quantized")
+        out["quant"] = run_layout(mq, scene, scene["scheme"], state, a.steps, a.warmup, "quantized",
+                                  specialize=not a.generic)
     if a.only == "fp32" or (a.only is None and not a.no_fp32):
         out["fp32"] = run_layout(mq, scene, WL.scheme_fp32(scene["params"]["dim"]), state, a.steps, a.warmup,
-                                 "fp32 layout")
+                                 "fp32 layout", specialize=not a.generic)
     del state
     torch.cuda.empty_cache()
     main_res = out.get("quant") or out["fp32"]
@@ -268,6 +365,7 @@ def main():
         "bytes_per_particle": main_res["bytes_per_particle"],
         "footprint_bytes_per_particle": round(main_res["footprint_bytes"] / n, 2),
         "sort_ms": round(main_res["sort_ms"], 3),
+        "kernels_specialized": not a.generic, "specialize_s": round(main_res["specialize_s"], 3),
         "kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in main_res["kernels"].items()},
         "roofline": rf,
         "cpu_baseline": cpu,

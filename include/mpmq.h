@@ -174,6 +174,18 @@ mpmq_status mpmq_step(mpmq_ctx *ctx, int32_t n_substeps);
 /* Substep counter (the Philox "step" of the next substep). */
 mpmq_status mpmq_step_count(mpmq_ctx *ctx, int64_t *out);
 
+/* Scheme specialization.  enable = 1: compiles, on the host with hipRTC,
+ * the fused substep and bootstrap P2G kernels with this context's scheme as
+ * compile-time constants (field kinds, bit offsets, masks, codec constants;
+ * the Philox key stays a run-time value), loads them on the current device
+ * and uses them from the next launch on.  The kernels are the same source
+ * under the same device flags, so every result equals the generic kernels'.
+ * Code objects are cached per process by (device, dimension, scheme): the
+ * first call for a scheme takes a few seconds, later ones none.  enable = 0
+ * returns to the generic kernels.  EDEVICE when the compiler or the loader
+ * fails (mpmq_last_error carries the compiler log). */
+mpmq_status mpmq_specialize(mpmq_ctx *ctx, int32_t enable);
+
 /* Encoder statistics collected by mpmq_step: level 0 (default) counts
  * saturations and NaN inputs; level 1 also counts round-ups and
  * round-downs per field (the dithering diagnostic of Sec. 8.1), at a small

@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
         "mpmq_reset_stats": [P],
         "mpmq_set_stats": [P, ct.c_int32],
         "mpmq_set_timing": [P, ct.c_int32],
+        "mpmq_specialize": [P, ct.c_int32],
         "mpmq_kernel_times": [P, ct.POINTER(mpmq_kernel_time), ct.c_int32, ct.POINTER(ct.c_int32)],
         "mpmq_adjoint_workspace": [P, ct.POINTER(mpmq_adjoint_spec), ct.POINTER(ct.c_int64)],
         "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, ct.c_int64, P, ct.POINTER(mpmq_adjoint_result)],
@@ -149,6 +150,7 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
             "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
+            "mpmq_specialize",
             "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_solve_scheme", "mpmq_solver_error", "mpmq_error_string",
             "mpmq_last_error"]
 
@@ -212,7 +214,7 @@ class Context:
     torch's current stream)."""
 
     def __init__(self, scheme: dict, params: dict, capacity: int, stream=None, track_ids=True,
-                 device=None):
+                 device=None, specialize=False):
         import torch
         L = load()
         self.scheme, self.params = scheme, params
@@ -241,6 +243,8 @@ class Context:
         self._h = h
         self.capacity = capacity
         self.n = 0
+        if specialize:
+            self.specialize(True)
 
     # -- C ABI calls ----------------------------------------------------------
     def encode(self, x, v, C, F):
@@ -303,6 +307,10 @@ class Context:
 
     def reset_stats(self):
         _check(load().mpmq_reset_stats(self._h), self._h)
+
+    def specialize(self, enable=True):
+        """mpmq_specialize: scheme-specialized fused kernels (same results)."""
+        _check(load().mpmq_specialize(self._h, 1 if enable else 0), self._h)
 
     def set_timing(self, enable=True):
         _check(load().mpmq_set_timing(self._h, 1 if enable else 0), self._h)

@@ -21,9 +21,20 @@ template <typename P> __device__ __forceinline__ P opaque(P v) {
 
 // The scheme lives in device memory that no kernel writes; reading it
 // through the constant address space keeps every field in scalar registers.
+// A specialized build defines MPMQ_SCHEME_CONST (a DevScheme initializer):
+// the kernels then read that compile-time constant instead, so kinds, bit
+// offsets and codec constants fold into the code.  The Philox key is always
+// read from the run-time copy (seed_ref), so one specialized build serves
+// every seed.
 typedef const __attribute__((address_space(4))) DevScheme *SchemeRef;
-__device__ __forceinline__ SchemeRef scheme_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
 typedef const __attribute__((address_space(4))) DevField *FieldRef;
+__device__ __forceinline__ SchemeRef seed_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
+#ifdef MPMQ_SCHEME_CONST
+static constexpr DevScheme kSchemeConst = MPMQ_SCHEME_CONST;
+__device__ __forceinline__ SchemeRef scheme_ref(const DevScheme *) { return (SchemeRef)&kSchemeConst; }
+#else
+__device__ __forceinline__ SchemeRef scheme_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
+#endif
 
 
 // ---------------------------------------------------------------------------
@@ -118,6 +129,7 @@ struct Draws {
     uint32_t r[2][4];
     int tag[2];
     uint32_t slot, step, ptag, seed_lo, seed_hi;
+    // s: the run-time scheme copy (seed_ref), which holds the key
     __device__ __forceinline__ void init(SchemeRef s, uint32_t slot_, uint32_t step_, uint32_t tag_) {
         tag[0] = tag[1] = -1;
         slot = slot_;
@@ -304,6 +316,17 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
 }
 
 
+
+// Decodes the whole record.
+template <int DIM, typename T>
+__device__ __forceinline__ void decode_all(const DevScheme *sp, const uint32_t *words, int64_t cap, uint32_t p4,
+                                           double *xv, T *vv, T *Cv, T *Fv) {
+    SchemeRef s = scheme_ref(sp);
+    dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xv);
+    dec_field<DIM, 1, T>(&s->f[1], words, cap, p4, vv);
+    dec_field<DIM, 2, T>(&s->f[2], words, cap, p4, Cv);
+    dec_field<DIM, 3, T>(&s->f[3], words, cap, p4, Fv);
+}
 
 // Encodes all four fields in placement order; qx.. receive the stored values.
 template <int DIM, bool RS>

@@ -1,8 +1,18 @@
 // mpmq_internal.hpp -- descriptors shared by the host runtime and the gfx950
 // kernels of the quantized MLS-MPM library (not part of the public ABI).
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string>
+#else
+// runtime compilation (hipRTC): the HIP runtime header is implicit
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint16_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
 
 namespace mpmq {
 
@@ -82,10 +92,8 @@ struct Scratch {
 
 struct WorkItem { int32_t block, p0, p1, pad; };
 
+#ifndef __HIPCC_RTC__
 // ---- launchers (kernels.hip) ----
-struct Launch {
-    hipStream_t stream;
-};
 
 hipError_t launch_encode(int dim, int wm, const DevScheme *s, const float *x, const float *v,
                          const float *C, const float *F, int64_t n, int64_t cap, uint32_t *words,
@@ -108,9 +116,20 @@ hipError_t launch_items(const uint32_t *cell_start, const uint32_t *block_items_
 hipError_t launch_gather_u32(const uint32_t *in, const uint32_t *perm, uint32_t *out, int64_t n,
                              hipStream_t st);
 hipError_t launch_copy_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
+// Kernels compiled at run time with a context's scheme as constants
+// (jit.hip); null entries fall back to the generic kernels.
+struct JitKernels {
+    hipFunction_t substep[2];  // k_substep<dim, RS = false / true>
+    hipFunction_t p2g;         // k_p2g<dim>
+};
+// Compiles (once per process, scheme and device) and loads the specialized
+// kernels for the current device.  Returns false with a message on failure.
+bool jit_kernels(int dim, const DevScheme &ds, JitKernels *out, std::string *err);
+
 hipError_t launch_p2g(int dim, int wm, const DevScheme *s, const DevParams &p, const uint32_t *words,
                       int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
-                      GNode *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st);
+                      GNode *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st,
+                      const JitKernels *jit = nullptr);
 hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *gnxt,
                               uint32_t *flags_cur, uint32_t *flags_nxt, int64_t nblocks,
                               uint64_t *stats, hipStream_t st);
@@ -118,7 +137,8 @@ hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblo
 hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &p, uint32_t *words,
                           int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
                           const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, uint32_t step,
-                          int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st);
+                          int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st,
+                          const JitKernels *jit = nullptr);
 
 // Adjoint (adjoint.hip).  lam buffers: float32 rows x[d], v[d], C[d*d],
 // F[d*d] of n each; nadj: one float4 per grid node; acc: binary64 z, G[4],
@@ -133,5 +153,7 @@ hipError_t launch_adj_range(int dim, const DevScheme *s, const uint32_t *words, 
                             hipStream_t st);
 hipError_t launch_adj_unpermute(const float *lam, const uint32_t *ids, int64_t n, int rows, float *out,
                                 hipStream_t st);
+
+#endif  // __HIPCC_RTC__
 
 }  // namespace mpmq

@@ -185,7 +185,10 @@ struct mpmq_ctx {
     std::vector<EventPair> events;
     std::map<std::string, std::pair<int64_t, double>> times;
     std::string err;
+    JitKernels jit{};
+    bool use_jit = false;
 
+    const JitKernels *jit_ptr() const { return use_jit ? &jit : nullptr; }
     uint32_t *u32(int64_t off) { return reinterpret_cast<uint32_t *>(scratch + off); }
     uint64_t *stats() { return reinterpret_cast<uint64_t *>(scratch + sp.stats); }
     uint32_t *flags(int i) { return u32(sp.flags) + (int64_t)i * sp.nblocks; }
@@ -299,7 +302,7 @@ mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
     if (!c->p2g_ready) {
         Timed t(c, "p2g");
         HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
-                             c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st), "p2g");
+                             c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st, c->jit_ptr()), "p2g");
     }
     {
         Timed t(c, "grid_update");
@@ -311,7 +314,8 @@ mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
         Timed t(c, "substep");
         HIPCHK(c, launch_substep(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                                  c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
-                                 next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st), "substep");
+                                 next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st, c->jit_ptr()),
+               "substep");
     }
     c->p2g_ready = !next_sorts;
     c->step = s + 1;
@@ -457,7 +461,7 @@ struct AdjRun {
         if (r != MPMQ_OK) return r;
         hipStream_t st = c->stream;
         HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, words, c->cap_pad, c->items(), c->n_items(),
-                             c->launch_grid, c->grid[0], c->flags(0), c->stats(), st), "adjoint: p2g");
+                             c->launch_grid, c->grid[0], c->flags(0), c->stats(), st, c->jit_ptr()), "adjoint: p2g");
         HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[0], c->grid[1], c->flags(0), c->flags(1), c->sp.nblocks,
                                      c->stats(), st), "adjoint: grid update");
         {
@@ -685,6 +689,20 @@ mpmq_status mpmq_set_stats(mpmq_ctx *c, int32_t level) {
     if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
     if (level < 0 || level > 1) return fail(c, MPMQ_EINVAL, "stats level must be 0 or 1");
     c->stats_level = level;
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_specialize(mpmq_ctx *c, int32_t enable) {
+    if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
+    if (!enable) {
+        c->use_jit = false;
+        return MPMQ_OK;
+    }
+    std::string err;
+    JitKernels k{};
+    if (!jit_kernels(c->dim, c->ds, &k, &err)) return fail(c, MPMQ_EDEVICE, "specialize: " + err);
+    c->jit = k;
+    c->use_jit = true;
     return MPMQ_OK;
 }
 

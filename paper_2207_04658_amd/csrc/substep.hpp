@@ -1,0 +1,513 @@
+// substep.hpp -- gfx950 device code of the fused substep and of the
+// bootstrap P2G: exact fixed-point P2G into an LDS node tile, G2P from the
+// tile, the per-particle update, the dithered encode and store.  Compiled
+// into libmpmq.so for any scheme read at run time, and (when a context asks
+// for it) compiled again at run time with the context's scheme as a
+// compile-time constant.
+#pragma once
+#include "mpmq_device.hpp"
+
+namespace mpmq {
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void flush_stats(const LaneStats &ls, uint64_t *stats) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const uint32_t up = wave_sum(ls.ud[f] & 0xffffu);
+        const uint32_t dn = wave_sum(ls.ud[f] >> 16);
+        const uint32_t sat = wave_sum((ls.sat >> (8 * f)) & 0xffu);
+        const uint32_t nan = wave_sum((ls.nan >> (8 * f)) & 0xffu);
+        if (__lane_id() == 0) {
+            if (up) atomicAdd((unsigned long long *)&stats[ST_UP + f], (unsigned long long)up);
+            if (dn) atomicAdd((unsigned long long *)&stats[ST_DOWN + f], (unsigned long long)dn);
+            if (sat) atomicAdd((unsigned long long *)&stats[ST_SAT + f], (unsigned long long)sat);
+            if (nan) atomicAdd((unsigned long long *)&stats[ST_NAN + f], (unsigned long long)nan);
+        }
+    }
+}
+
+__device__ __forceinline__ void add_stat(uint64_t *stats, int slot, uint32_t lane_value) {
+    const uint32_t s = wave_sum(lane_value);
+    if (__lane_id() == 0 && s) atomicAdd((unsigned long long *)&stats[slot], (unsigned long long)s);
+}
+
+
+// Fixed-point conversion: round(v * 2^32) as two's complement int64 for
+// |v| < 2^19, via binary64: fma(w, x, 1.5*2^52) puts the rounded integer in
+// the low mantissa bits (exponent field constant), the subtraction removes
+// the offset.  w * x carries the 2^32 scale already.
+__device__ __forceinline__ unsigned long long fixp(double w, double xs) {
+    return (unsigned long long)__double_as_longlong(fma(w, xs, FIX_MAGIC)) - FIX_MAGIC_BITS;
+}
+
+// P2G straight into the grid buffer, for a particle whose stencil left its tile.
+template <int DIM>
+__device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, const double (*w)[3],
+                                           const double *q, const double (*ac)[DIM], GNode *__restrict__ gout,
+                                           uint32_t *__restrict__ flags) {
+    constexpr int NST = Geo<DIM>::NST;
+#pragma unroll
+    for (int s = 0; s < NST; ++s) {
+        const int o[3] = {s % 3, (s / 3) % 3, s / 9};
+        int ijk[DIM];
+        double wt = 1.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            wt *= w[a][o[a]];
+        }
+        unsigned long long *g = gout[node_index<DIM>(ijk, P.nb)].q;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            double val = q[a];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) val += ac[b][a] * (double)o[b];
+            atomicAdd(g + a, fixp(wt, val));
+        }
+        atomicAdd(g + 3, fixp(wt, FIX_ONE));
+        flags[block_of<DIM>(ijk, P.nb)] = 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2G of one particle from its decoded (quantized) state.  Node i receives,
+// per unit particle mass, w_i (v + (A/m)(x_i - x_p)) and w_i, accumulated as
+// exact 64-bit fixed point (LDS integer atomics: float LDS atomics are an
+// order of magnitude slower on this part, and integer sums are
+// order-independent).
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
+                                             const float *C, const float *F, const int *origin,
+                                             unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
+                                             uint32_t *__restrict__ flags, uint32_t &fallback) {
+    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
+    constexpr float LIM = 4096.0f;  // |q|, |a_b| <= 2^12 keeps every term below 2^19
+    int base[DIM];
+    float fx[DIM];
+    stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
+    double w[DIM][3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float wf[3];
+        bspline(fx[a], wf);
+        w[a][0] = wf[0];
+        w[a][1] = wf[1];
+        w[a][2] = wf[2];
+    }
+    // fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + lambda J (J-1) I
+    float R[D2];
+    float J;
+    if constexpr (DIM == 2) {
+        polar2(F, R);
+        J = F[0] * F[3] - F[1] * F[2];
+    } else {
+        polar3(F, R);
+        J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+            F[2] * (F[3] * F[7] - F[4] * F[6]);
+    }
+    // A / m_p = -4 dt / (rho dx^2) tau + C
+    float Am[D2];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            float t = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
+            t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
+            Am[i * DIM + j] = P.stress_over_m * t + C[i * DIM + j];
+        }
+    // node value = w (q + sum_b a_b o_b), q = v - (A/m) f dx, a_b = (A/m)[:, b] dx, scaled by 2^32
+    double q[DIM], ac[DIM][DIM];  // ac[b][a]
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float t = v[a];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const float ab = fminf(fmaxf(Am[a * DIM + b] * P.dx, -LIM), LIM);
+            ac[b][a] = (double)ab * FIX_ONE;
+            t -= ab * fx[b];
+        }
+        q[a] = (double)fminf(fmaxf(t, -LIM), LIM) * FIX_ONE;
+    }
+    bool in_tile = true;
+    int l[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        l[a] = base[a] - origin[a];
+        in_tile &= (l[a] >= 0) && (l[a] <= TB - 3);
+    }
+    if (in_tile) {
+        const int l0 = (DIM == 3) ? (l[DIM - 1] * TB + l[1]) * TB + l[0] : l[1] * TB + l[0];
+        // node values stepped along each axis (q + sum_b a_b o_b by additions)
+        if constexpr (DIM == 3) {
+            double vz[3] = {q[0], q[1], q[2]};
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz) {
+                if (oz > 0)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) vz[a] += ac[2][a];
+                double vzy[3] = {vz[0], vz[1], vz[2]};
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+                    if (oy > 0)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) vzy[a] += ac[1][a];
+                    const double wzy = w[2][oz] * w[1][oy];
+                    double val[3] = {vzy[0], vzy[1], vzy[2]};
+#pragma unroll
+                    for (int ox = 0; ox < 3; ++ox) {
+                        if (ox > 0)
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) val[a] += ac[0][a];
+                        const double wt = wzy * w[0][ox];
+                        const int idx = l0 + (oz * TB + oy) * TB + ox;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
+                        atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
+                    }
+                }
+            }
+        } else {
+            double vy[2] = {q[0], q[1]};
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+                if (oy > 0)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) vy[a] += ac[1][a];
+                double val[2] = {vy[0], vy[1]};
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox) {
+                    if (ox > 0)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) val[a] += ac[0][a];
+                    const double wt = w[1][oy] * w[0][ox];
+                    const int idx = l0 + oy * TB + ox;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
+                    atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
+                }
+            }
+        }
+    } else {
+        fallback += 1;
+        p2g_global<DIM>(P, base, w, q, ac, gout, flags);
+    }
+}
+
+// tile helpers ---------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void tile_origin(int block, int nb, int *origin) {
+    constexpr int B = Geo<DIM>::BLK;
+    origin[0] = (block % nb) * B - 1;
+    if constexpr (DIM == 3) {
+        origin[1] = ((block / nb) % nb) * B - 1;
+        origin[2] = (block / (nb * nb)) * B - 1;
+    } else {
+        origin[1] = (block / nb) * B - 1;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ bool tile_node(int t, const int *origin, int res, int *ijk) {
+    constexpr int TB = Geo<DIM>::TB;
+    ijk[0] = origin[0] + t % TB;
+    if constexpr (DIM == 3) {
+        ijk[1] = origin[1] + (t / TB) % TB;
+        ijk[2] = origin[2] + t / (TB * TB);
+    } else {
+        ijk[1] = origin[1] + t / TB;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) ok &= (ijk[a] >= 0) && (ijk[a] < res);
+    return ok;
+}
+
+template <int DIM>
+__device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin,
+                                           const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
+                                           uint32_t *__restrict__ flags) {
+    constexpr int TN = Geo<DIM>::TN;
+    for (int t = threadIdx.x; t < TN; t += WG) {
+        const unsigned long long a0 = acc[t], a1 = acc[TN + t], a2 = acc[2 * TN + t], m = acc[3 * TN + t];
+        if ((a0 | a1 | a2 | m) != 0ull) {
+            int ijk[DIM];
+            if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached: contributions stay in-grid
+            unsigned long long *g = gout[node_index<DIM>(ijk, P.nb)].q;
+            atomicAdd(g + 0, a0);
+            atomicAdd(g + 1, a1);
+            if (DIM == 3) atomicAdd(g + 2, a2);
+            atomicAdd(g + 3, m);
+            flags[block_of<DIM>(ijk, P.nb)] = 1u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work-item walk.  Work-groups are dispatched round-robin over the
+// 8 XCDs (each with its own L2), so work-group b runs on XCD b % 8; XCD x
+// walks the contiguous range [x*chunk, (x+1)*chunk) of the block-ordered
+// items, so spatially adjacent tiles (which share halo nodes) meet in the
+// same L2.  The trip count depends only on blockIdx: uniform per group.
+// ---------------------------------------------------------------------------
+struct ItemWalk {
+    uint32_t first, stride, end;
+    __device__ ItemWalk(uint32_t nit) {
+        const uint32_t x = blockIdx.x & 7u, per = gridDim.x >> 3;
+        const uint32_t chunk = (nit + 7u) >> 3;
+        first = x * chunk + (blockIdx.x >> 3);
+        stride = per;
+        end = min(nit, (x + 1u) * chunk);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// bootstrap P2G from the packed state (after a sort or an encode)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_p2g(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
+                                            int64_t cap, const WorkItem *__restrict__ items,
+                                            const uint32_t *__restrict__ n_items, GNode *__restrict__ gout,
+                                            uint32_t *__restrict__ flags, uint64_t *stats) {
+    constexpr int TN = Geo<DIM>::TN, D2 = DIM * DIM;
+    __shared__ unsigned long long acc[4 * TN];
+    const uint32_t nit = *n_items;
+    uint32_t fallback = 0;
+    const ItemWalk walk(nit);
+    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
+        const WorkItem it = items[item];
+        int origin[DIM];
+        tile_origin<DIM>(it.block, P.nb, origin);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 4 * TN; t += WG) acc[t] = 0ull;
+        __syncthreads();
+        for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
+            double xd[DIM];
+            float v[DIM], C[D2], F[D2];
+            decode_all<DIM, float>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
+            p2g_particle<DIM>(P, xd, v, C, F, origin, acc, gout, flags, fallback);
+        }
+        __syncthreads();
+        tile_flush<DIM>(P, origin, acc, gout, flags);
+    }
+    add_stat(stats, ST_FALLBACK, fallback);
+}
+
+
+// ---------------------------------------------------------------------------
+// fused substep: G2P -> update -> dithered encode + store -> P2G (next step)
+// ---------------------------------------------------------------------------
+
+// G2P from the LDS tile, separable in the three axes:
+// v' = sum_i w v_i and S_b = sum_i w (o_b - f_b) v_i, C' = 4/dx S.
+template <int DIM>
+__device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, const float (*wx)[3],
+                                         const float (*wd)[3], float *nv, float (*S)[DIM]) {
+    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN;
+    if constexpr (DIM == 3) {
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+            float P00[3] = {0.f, 0.f, 0.f}, P01[3] = {0.f, 0.f, 0.f}, P10[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+                float R0[3] = {0.f, 0.f, 0.f}, R1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox) {
+                    const int idx = l0 + (oz * TB + oy) * TB + ox;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float vi = gv[a * TN + idx];
+                        R0[a] += wx[0][ox] * vi;
+                        R1[a] += wd[0][ox] * vi;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    P00[a] += wx[1][oy] * R0[a];
+                    P01[a] += wd[1][oy] * R0[a];
+                    P10[a] += wx[1][oy] * R1[a];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                nv[a] += wx[2][oz] * P00[a];
+                S[0][a] += wx[2][oz] * P10[a];
+                S[1][a] += wx[2][oz] * P01[a];
+                S[2][a] += wd[2][oz] * P00[a];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            float R0[2] = {0.f, 0.f}, R1[2] = {0.f, 0.f};
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const int idx = l0 + oy * TB + ox;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float vi = gv[a * TN + idx];
+                    R0[a] += wx[0][ox] * vi;
+                    R1[a] += wd[0][ox] * vi;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                nv[a] += wx[1][oy] * R0[a];
+                S[0][a] += wx[1][oy] * R1[a];
+                S[1][a] += wd[1][oy] * R0[a];
+            }
+        }
+    }
+}
+
+// G2P straight from the grid buffer, for a particle whose stencil left its tile.
+template <int DIM>
+__device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int nb, const int *base,
+                                                     const float (*wx)[3], const float (*wd)[3], float *nv,
+                                                     float (*S)[DIM]) {
+    constexpr int NST = Geo<DIM>::NST;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        int ijk[DIM];
+        float w = 1.0f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ijk[a] = base[a] + o[a];
+            w *= wx[a][o[a]];
+        }
+        const float4 g = reinterpret_cast<const float4 *>(gcur + node_index<DIM>(ijk, nb))[0];
+        const float vi[3] = {g.x, g.y, g.z};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            nv[a] += w * vi[a];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                float wdb = 1.0f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) wdb *= (c == b) ? wd[c][o[c]] : wx[c][o[c]];
+                S[b][a] += wdb * vi[a];
+            }
+        }
+    }
+}
+
+template <int DIM, bool RS>
+__global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__ sch, DevParams P, uint32_t *words,
+                                                int64_t cap, const WorkItem *__restrict__ items,
+                                                const uint32_t *__restrict__ n_items,
+                                                const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
+                                                uint32_t *__restrict__ flags, uint32_t step, int do_p2g,
+                                                int collect_stats, uint64_t *stats) {
+    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
+    __shared__ float gv[DIM * TN];
+    __shared__ unsigned long long acc[4 * TN];
+    const uint32_t nit = *n_items;
+    uint32_t fallback = 0;
+    LaneStats ls;
+    ls.clear();
+    const ItemWalk walk(nit);
+    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
+        const WorkItem it = items[item];
+        int origin[DIM];
+        tile_origin<DIM>(it.block, P.nb, origin);
+        __syncthreads();
+        for (int t = threadIdx.x; t < TN; t += WG) {
+            int ijk[DIM];
+            float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (tile_node<DIM>(t, origin, P.res, ijk))
+                g = reinterpret_cast<const float4 *>(gcur + node_index<DIM>(ijk, P.nb))[0];
+            gv[t] = g.x;
+            gv[TN + t] = g.y;
+            if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
+        }
+        if (do_p2g)
+            for (int t = threadIdx.x; t < 4 * TN; t += WG) acc[t] = 0ull;
+        __syncthreads();
+        for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
+            SchemeRef sp = scheme_ref(sch);
+            const uint32_t p4 = (uint32_t)p * 4u;
+            double xd[DIM];
+            float F[D2];
+            dec_field<DIM, 0, double>(&sp->f[0], words, cap, p4, xd);
+            dec_field<DIM, 3, float>(&sp->f[3], words, cap, p4, F);
+            int base[DIM];
+            float fx[DIM], wx[DIM][3], wd[DIM][3];
+            stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
+            bool in_tile = true;
+            int l[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                bspline(fx[a], wx[a]);
+#pragma unroll
+                for (int o = 0; o < 3; ++o) wd[a][o] = wx[a][o] * ((float)o - fx[a]);
+                l[a] = base[a] - origin[a];
+                in_tile &= (l[a] >= 0) && (l[a] <= TB - 3);
+            }
+            float nv[DIM], S[DIM][DIM];  // S[b][a]
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                nv[a] = 0.0f;
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) S[b][a] = 0.0f;
+            }
+            if (in_tile) {
+                const int l0 = (DIM == 3) ? (l[DIM - 1] * TB + l[1]) * TB + l[0] : l[1] * TB + l[0];
+                g2p_tile<DIM>(gv, l0, wx, wd, nv, S);
+            } else {
+                fallback += 1;
+                g2p_global<DIM>(gcur, P.nb, base, wx, wd, nv, S);
+            }
+            // update: x' = x + dt v' (binary64), C' = 4/dx S, F' = (I + dt C') F
+            double xn[DIM];
+            float Cn[D2], Fn[D2];
+            {
+#pragma clang fp contract(off)
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) xn[a] = xd[a] + P.dt_d * (double)nv[a];
+            }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] = 4.0f * P.inv_dx * S[b][a];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+                for (int j = 0; j < DIM; ++j) {
+                    float t = F[i * DIM + j];
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) t += P.dt * Cn[i * DIM + k] * F[k * DIM + j];
+                    Fn[i * DIM + j] = t;
+                }
+            // dithered encode (Eq. 11), streamed in place in placement order
+            Draws rnd;
+            rnd.init(seed_ref(sch), (uint32_t)p, step, 1u);
+            OutStream os{words, cap, p4, 0ull, 0, 0};
+            double qx[DIM];
+            float qv[DIM], qC[D2], qF[D2];
+            encode_record<DIM, RS>(sch, xn, nv, Cn, Fn, rnd, os, ls, qx, qv, qC, qF);
+            // P2G of the stored (quantized) state for the next substep (Eq. 1)
+            if (do_p2g) p2g_particle<DIM>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
+        }
+        __syncthreads();
+        if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags);
+        if (collect_stats) {
+            flush_stats(ls, stats);
+            ls.clear();
+        }
+    }
+    add_stat(stats, ST_FALLBACK, fallback);
+}
+
+
+}  // namespace mpmq
