@@ -333,7 +333,14 @@ template <int DIM, bool RS>
 __device__ __forceinline__ void encode_record(const DevScheme *sp, const double *x, const float *v,
                                               const float *C, const float *F, Draws &rnd, OutStream &os,
                                               LaneStats &ls, double *qx, float *qv, float *qC, float *qF) {
+    // with a run-time scheme the four fields are one loop (the field order is
+    // data); with a compile-time scheme it unrolls and every word boundary of
+    // the stream is known at compile time
+#ifdef MPMQ_SCHEME_CONST
+#pragma unroll
+#else
 #pragma unroll 1
+#endif
     for (int slot = 0; slot < 4; ++slot) {
         SchemeRef s = scheme_ref(sp);
         const int fid = s->order[slot];
