@@ -22,7 +22,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-FIELDS = {"x": 0, "v": 1, "C": 2, "F": 3}
+FIELDS = {"x": 0, "v": 1, "C": 2, "F": 3, "J": 4}
+MATERIALS = {"elastic": 0, "fluid": 1}
+
+
+def slot3_name(scheme: dict) -> str:
+    """"F" (elastic) or "J" (fluid): the field in the fourth state slot."""
+    return "J" if any(f["field"] == "J" for f in scheme["fields"]) else "F"
+
+
+def nc3(scheme: dict) -> int:
+    return 1 if slot3_name(scheme) == "J" else scheme["dim"] ** 2
 KINDS = {"fixed": 0, "shared_exp": 1, "raw_f32": 2}
 
 
@@ -41,7 +51,7 @@ class _Params(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("grid_res", ct.c_int32), ("bound_cells", ct.c_int32),
                 ("sort_every", ct.c_int32), ("dt", ct.c_double), ("gravity", ct.c_double * 3),
                 ("E", ct.c_double), ("nu", ct.c_double), ("rho", ct.c_double),
-                ("p_vol", ct.c_double)]
+                ("p_vol", ct.c_double), ("material", ct.c_int32), ("pad", ct.c_int32)]
 
 
 class _Stat(ct.Structure):
@@ -124,6 +134,7 @@ def make_params(params: dict) -> _Params:
     p.nu = params["nu"]
     p.rho = params["rho"]
     p.p_vol = params["p_vol"]
+    p.material = MATERIALS[params.get("material", "elastic")]
     return p
 
 
@@ -151,8 +162,8 @@ def philox(ctr, key):
     return out
 
 
-def stats_dict(st):
-    names = ["x", "v", "C", "F"]
+def stats_dict(st, scheme=None):
+    names = ["x", "v", "C", slot3_name(scheme) if scheme else "F"]
     return {names[i]: {"sat": st[i].sat, "nan": st[i].nan, "up": st[i].up, "down": st[i].down}
             for i in range(4)}
 
@@ -166,7 +177,7 @@ def encode(scheme: dict, x, v, C, F, step=0, tag=2):
     n = x.shape[1]
     v = np.ascontiguousarray(v, dtype=dt).reshape(dim, n)
     C = np.ascontiguousarray(C, dtype=dt).reshape(dim * dim, n)
-    F = np.ascontiguousarray(F, dtype=dt).reshape(dim * dim, n)
+    F = np.ascontiguousarray(F, dtype=dt).reshape(nc3(scheme), n)
     _, _, _, W = layout(scheme)
     words = np.zeros((W, n), dtype=np.uint32)
     st = (_Stat * 4)()
@@ -175,7 +186,7 @@ def encode(scheme: dict, x, v, C, F, step=0, tag=2):
             _ptr(words), ct.cast(st, ct.c_void_p))
     if rc:
         raise ValueError("invalid scheme")
-    return words, stats_dict(st)
+    return words, stats_dict(st, scheme)
 
 
 def decode(scheme: dict, words):
@@ -183,7 +194,7 @@ def decode(scheme: dict, words):
     words = np.ascontiguousarray(words, dtype=np.uint32)
     n = words.shape[1]
     x = np.zeros((dim, n)); v = np.zeros((dim, n))
-    C = np.zeros((dim * dim, n)); F = np.zeros((dim * dim, n))
+    C = np.zeros((dim * dim, n)); F = np.zeros((nc3(scheme), n))
     rc = lib().orc_decode(ct.byref(make_scheme(scheme)), n, _ptr(words), _ptr(x), _ptr(v), _ptr(C), _ptr(F))
     if rc:
         raise ValueError("invalid scheme")
@@ -210,13 +221,17 @@ def _nodes(params):
     return params["grid_res"] ** params["dim"]
 
 
+def _nc3p(params):
+    return 1 if params.get("material", "elastic") == "fluid" else params["dim"] ** 2
+
+
 def p2g(params: dict, x, v, C, F):
     dim = params["dim"]
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(dim, -1)
     n = x.shape[1]
     v = np.ascontiguousarray(v, dtype=np.float64).reshape(dim, n)
     C = np.ascontiguousarray(C, dtype=np.float64).reshape(dim * dim, n)
-    F = np.ascontiguousarray(F, dtype=np.float64).reshape(dim * dim, n)
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(_nc3p(params), n)
     gm = np.zeros(_nodes(params))
     gmom = np.zeros((dim, _nodes(params)))
     lib().orc_p2g(ct.byref(make_params(params)), n, _ptr(x), _ptr(v), _ptr(C), _ptr(F), _ptr(gm), _ptr(gmom))
@@ -234,10 +249,10 @@ def g2p(params: dict, x, F, grid_v):
     dim = params["dim"]
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(dim, -1)
     n = x.shape[1]
-    F = np.ascontiguousarray(F, dtype=np.float64).reshape(dim * dim, n)
+    F = np.ascontiguousarray(F, dtype=np.float64).reshape(_nc3p(params), n)
     gv = np.ascontiguousarray(grid_v, dtype=np.float64).reshape(dim, -1)
     x1 = np.zeros((dim, n)); v1 = np.zeros((dim, n))
-    C1 = np.zeros((dim * dim, n)); F1 = np.zeros((dim * dim, n))
+    C1 = np.zeros((dim * dim, n)); F1 = np.zeros((_nc3p(params), n))
     lib().orc_g2p(ct.byref(make_params(params)), n, _ptr(x), _ptr(F), _ptr(gv), _ptr(x1), _ptr(v1), _ptr(C1), _ptr(F1))
     return x1, v1, C1, F1
 
@@ -254,6 +269,7 @@ class Sim:
     """The oracle simulation: packed words in, packed words out, one substep at a time."""
 
     def __init__(self, scheme: dict, params: dict, words):
+        self.scheme = scheme
         self._s = make_scheme(scheme)
         self._p = make_params(params)
         self.words0 = np.ascontiguousarray(words, dtype=np.uint32)
@@ -279,7 +295,7 @@ class Sim:
     def stats(self):
         st = (_Stat * 4)()
         lib().orc_sim_stats(self._h, ct.cast(st, ct.c_void_p))
-        return stats_dict(st)
+        return stats_dict(st, self.scheme)
 
     @property
     def step_count(self):
@@ -304,10 +320,15 @@ def pack_state(x, v, C, F):
     return np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64) for a in (x, v, C, F)], axis=0))
 
 
-def field_rows(dim):
-    """Row ranges of x, v, C, F in a packed state."""
+def field_rows(dim, material="elastic"):
+    """Row ranges of x, v, C, F (elastic) or J (fluid) in a packed state."""
     d2 = dim * dim
-    return {"x": (0, dim), "v": (dim, 2 * dim), "C": (2 * dim, 2 * dim + d2), "F": (2 * dim + d2, 2 * dim + 2 * d2)}
+    rows = {"x": (0, dim), "v": (dim, 2 * dim), "C": (2 * dim, 2 * dim + d2)}
+    if material == "fluid":
+        rows["J"] = (2 * dim + d2, 2 * dim + d2 + 1)
+    else:
+        rows["F"] = (2 * dim + d2, 2 * dim + 2 * d2)
+    return rows
 
 
 def step_exact(params: dict, state):
@@ -349,7 +370,7 @@ def adjoint_full(params: dict, states, kind="com", axis=1):
     stored state), g = the sum of its squares (the accumulated squared
     gradient of Eq. 8), A = the sum of its absolute values, and lambda_0."""
     dim = params["dim"]
-    rows = field_rows(dim)
+    rows = field_rows(dim, params.get("material", "elastic"))
     T = len(states) - 1
     z, lam = objective(params, states[T], kind, axis)
     G = {f: 0.0 for f in rows}

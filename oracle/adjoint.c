@@ -165,6 +165,13 @@ static int64_t nnodes(const orc_params *p)
     return p->dim == 2 ? n * n : n * n * n;
 }
 
+/* rows of a state: x, v, C, then F (elastic) or J (fluid) */
+static int nrows(const orc_params *p)
+{
+    int d = p->dim;
+    return 2 * d + d * d + (p->material == ORC_FLUID ? 1 : d * d);
+}
+
 /* state pointers */
 typedef struct { const double *x, *v, *C, *F; } cstate;
 typedef struct { double *x, *v, *C, *F; } mstate;
@@ -207,7 +214,8 @@ int orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double 
     cstate s = cview(in, dim, n);
     cstate lo = cview(lam_out, dim, n);
     mstate li = mview(lam_in, dim, n);
-    memset(lam_in, 0, sizeof(double) * (size_t)(n * (2 * dim + 2 * D2)));
+    memset(lam_in, 0, sizeof(double) * (size_t)(n * nrows(p)));
+    const int fluid = p->material == ORC_FLUID;
     /* forward grid (needed by both halves) */
     double *gm = calloc((size_t)nodes, sizeof(double));
     double *gmom = calloc((size_t)nodes * dim, sizeof(double));
@@ -224,7 +232,8 @@ int orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double 
     for (int64_t q = 0; q < n; ++q) {
         double xp[3], Fp[9], nC[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int a = 0; a < dim; ++a) xp[a] = s.x[a * n + q];
-        for (int c = 0; c < D2; ++c) Fp[c] = s.F[c * n + q];
+        if (!fluid)
+            for (int c = 0; c < D2; ++c) Fp[c] = s.F[c * n + q];
         int base[3];
         double fx[3], w[3][3], dw[3][3];
         weights(p, xp, base, fx, w, dw);
@@ -239,19 +248,28 @@ int orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double 
         }
         double lx[3], lv[3], lC[9], lF[9];
         for (int a = 0; a < dim; ++a) { lx[a] = lo.x[a * n + q]; lv[a] = lo.v[a * n + q]; }
-        for (int c = 0; c < D2; ++c) { lC[c] = lo.C[c * n + q]; lF[c] = lo.F[c * n + q]; }
-        /* F' = (I + dt C') F */
-        for (int i = 0; i < dim; ++i)
-            for (int j = 0; j < dim; ++j) {
-                double aF = 0.0, aC = 0.0;
-                for (int k = 0; k < dim; ++k) {
-                    double Mki = ((k == i) ? 1.0 : 0.0) + p->dt * nC[k * dim + i];
-                    aF += Mki * lF[k * dim + j];                 /* (I + dt C')^T lF' */
-                    aC += lF[i * dim + k] * Fp[j * dim + k];     /* lF' F^T */
+        for (int c = 0; c < D2; ++c) lC[c] = lo.C[c * n + q];
+        if (fluid) {
+            /* J' = J (1 + dt tr C') */
+            double lJ = lo.F[q], tr = 0.0;
+            for (int a = 0; a < dim; ++a) tr += nC[a * dim + a];
+            li.F[q] += lJ * (1.0 + p->dt * tr);
+            for (int a = 0; a < dim; ++a) lC[a * dim + a] += lJ * s.F[q] * p->dt;
+        } else {
+            for (int c = 0; c < D2; ++c) lF[c] = lo.F[c * n + q];
+            /* F' = (I + dt C') F */
+            for (int i = 0; i < dim; ++i)
+                for (int j = 0; j < dim; ++j) {
+                    double aF = 0.0, aC = 0.0;
+                    for (int k = 0; k < dim; ++k) {
+                        double Mki = ((k == i) ? 1.0 : 0.0) + p->dt * nC[k * dim + i];
+                        aF += Mki * lF[k * dim + j];                 /* (I + dt C')^T lF' */
+                        aC += lF[i * dim + k] * Fp[j * dim + k];     /* lF' F^T */
+                    }
+                    li.F[(i * dim + j) * n + q] += aF;
+                    lC[i * dim + j] += p->dt * aC;
                 }
-                li.F[(i * dim + j) * n + q] += aF;
-                lC[i * dim + j] += p->dt * aC;
-            }
+        }
         /* x' = x + dt v' */
         for (int a = 0; a < dim; ++a) { li.x[a * n + q] += lx[a]; lv[a] += p->dt * lx[a]; }
         /* v' = sum w v_i ; C' = D sum w v_i d^T, d = x_i - x_p */
@@ -297,8 +315,13 @@ int orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double 
     for (int64_t q = 0; q < n; ++q) {
         double xp[3], vp[3], Cp[9], Fp[9], tau[9], A[9];
         for (int a = 0; a < dim; ++a) { xp[a] = s.x[a * n + q]; vp[a] = s.v[a * n + q]; }
-        for (int c = 0; c < D2; ++c) { Cp[c] = s.C[c * n + q]; Fp[c] = s.F[c * n + q]; }
-        orc_kirchhoff(dim, Fp, mu, la, tau);
+        for (int c = 0; c < D2; ++c) Cp[c] = s.C[c * n + q];
+        if (fluid) {
+            orc_fluid_stress(dim, s.F[q], p->E, tau);
+        } else {
+            for (int c = 0; c < D2; ++c) Fp[c] = s.F[c * n + q];
+            orc_kirchhoff(dim, Fp, mu, la, tau);
+        }
         double sc = -p->dt * p->p_vol * D;
         for (int c = 0; c < D2; ++c) A[c] = sc * tau[c] + m * Cp[c];
         int base[3];
@@ -332,8 +355,15 @@ int orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double 
         for (int c = 0; c < D2; ++c) li.C[c * n + q] += m * lA[c];
         double lt[9], lFp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int c = 0; c < D2; ++c) lt[c] = sc * lA[c];
-        stress_vjp(dim, Fp, mu, la, lt, lFp);
-        for (int c = 0; c < D2; ++c) li.F[c * n + q] += lFp[c];
+        if (fluid) {
+            /* tau = E (J - 1) I */
+            double tr = 0.0;
+            for (int a = 0; a < dim; ++a) tr += lt[a * dim + a];
+            li.F[q] += p->E * tr;
+        } else {
+            stress_vjp(dim, Fp, mu, la, lt, lFp);
+            for (int c = 0; c < D2; ++c) li.F[c * n + q] += lFp[c];
+        }
     }
     free(gm); free(gmom); free(gv); free(lgv); free(lmom); free(lm);
     return 0;
@@ -344,10 +374,10 @@ int orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double 
 int orc_objective(const orc_params *p, int64_t n, const double *st, int objective, int axis, double *z,
                   double *lam)
 {
-    int dim = p->dim, D2 = dim * dim;
+    int dim = p->dim;
     double m = p->rho * p->p_vol;
     cstate s = cview(st, dim, n);
-    memset(lam, 0, sizeof(double) * (size_t)(n * (2 * dim + 2 * D2)));
+    memset(lam, 0, sizeof(double) * (size_t)(n * nrows(p)));
     mstate l = mview(lam, dim, n);
     double acc = 0.0;
     if (objective == 0) {

@@ -36,7 +36,19 @@
 #include <math.h>
 #include <string.h>
 
-static int ncomp_of(int field, int dim) { return (field == ORC_X || field == ORC_V) ? dim : dim * dim; }
+static int ncomp_of(int field, int dim)
+{
+    return (field == ORC_X || field == ORC_V) ? dim : field == ORC_J ? 1 : dim * dim;
+}
+/* state slot of a field: F and J share slot 3 */
+static int slot_of(int field) { return field == ORC_J ? 3 : field; }
+/* components of the scheme's slot-3 field */
+static int nc3_of(const orc_scheme *s)
+{
+    for (int i = 0; i < 4; ++i)
+        if (slot_of(s->f[i].field) == 3) return ncomp_of(s->f[i].field, s->dim);
+    return s->dim * s->dim;
+}
 
 int orc_validate(const orc_scheme *s)
 {
@@ -46,10 +58,10 @@ int orc_validate(const orc_scheme *s)
     int total = 0;
     for (int i = 0; i < 4; ++i) {
         const orc_field *f = &s->f[i];
-        if (f->field < 0 || f->field > 3 || seen[f->field]) return -1;
-        seen[f->field] = 1;
+        if (f->field < 0 || f->field > 4 || seen[slot_of(f->field)]) return -1;
+        seen[slot_of(f->field)] = 1;
         int nc = ncomp_of(f->field, s->dim);
-        if (f->rel_identity && f->field != ORC_F) return -1;
+        if (f->rel_identity && f->field != ORC_F && f->field != ORC_J) return -1;
         if (f->kind == ORC_FIXED) {
             if (f->bits < 1 || f->bits > 32) return -1;
             if (!(f->hi > f->lo) || !isfinite(f->lo) || !isfinite(f->hi)) return -1;
@@ -80,10 +92,10 @@ int orc_layout(const orc_scheme *s, int32_t *comp_offset, int32_t *field_offset,
     for (int i = 0; i < 4; ++i) {
         const orc_field *f = &s->f[i];
         int nc = ncomp_of(f->field, s->dim);
-        if (field_offset) field_offset[f->field] = off;
+        if (field_offset) field_offset[slot_of(f->field)] = off;
         if (f->kind == ORC_SHARED_EXP) off += f->exp_bits;
         for (int c = 0; c < nc; ++c) {
-            if (comp_offset) comp_offset[f->field * 9 + c] = off;
+            if (comp_offset) comp_offset[slot_of(f->field) * 9 + c] = off;
             off += f->bits;
         }
     }
@@ -267,16 +279,17 @@ static void encode_record(const orc_scheme *s, const double vals[4][9], uint32_t
     memset(rec, 0, sizeof(uint32_t) * (size_t)W);
     int off = 0;
     double draws[32];
-    dither_draws(s->seed, slot, step, tag, 2 * dim + 2 * dim * dim, draws);
+    dither_draws(s->seed, slot, step, tag, 2 * dim + dim * dim + nc3_of(s), draws);
     for (int i = 0; i < 4; ++i) {
         const orc_field *f = &s->f[i];
         int nc = ncomp_of(f->field, dim);
-        orc_stat *st = stats ? &stats[f->field] : 0;
-        /* canonical index of the field's first component: x, v, C, F */
-        int k = f->field == ORC_X ? 0 : f->field == ORC_V ? dim : f->field == ORC_C ? 2 * dim : 2 * dim + dim * dim;
+        int sl = slot_of(f->field);
+        orc_stat *st = stats ? &stats[sl] : 0;
+        /* canonical index of the field's first component: x, v, C, then F or J */
+        int k = sl == ORC_X ? 0 : sl == ORC_V ? dim : sl == ORC_C ? 2 * dim : 2 * dim + dim * dim;
         double rel[9];
         for (int c = 0; c < nc; ++c) {
-            double val = vals[f->field][c];
+            double val = vals[sl][c];
             if (f->rel_identity && (c % (dim + 1) == 0)) val = val - 1.0;
             rel[c] = val;
         }
@@ -311,7 +324,7 @@ static void decode_record(const orc_scheme *s, const uint32_t *rec, double vals[
     for (int i = 0; i < 4; ++i) {
         const orc_field *f = &s->f[i];
         int nc = ncomp_of(f->field, dim);
-        double *out = vals[f->field];
+        double *out = vals[slot_of(f->field)];
         if (f->kind == ORC_SHARED_EXP) {
             uint32_t codes[10];
             codes[0] = get_bits(rec, off, f->exp_bits);
@@ -339,7 +352,7 @@ static int encode_common(const orc_scheme *s, int64_t n, const float *xf, const 
 {
     int32_t W;
     if (orc_layout(s, 0, 0, 0, &W)) return -1;
-    int dim = s->dim;
+    int dim = s->dim, nc3 = nc3_of(s);
     uint32_t rec[32];
     for (int64_t p = 0; p < n; ++p) {
         double vals[4][9];
@@ -347,10 +360,8 @@ static int encode_common(const orc_scheme *s, int64_t n, const float *xf, const 
             vals[ORC_X][c] = xf ? (double)xf[c * n + p] : xd[c * n + p];
             vals[ORC_V][c] = vf ? (double)vf[c * n + p] : vd[c * n + p];
         }
-        for (int c = 0; c < dim * dim; ++c) {
-            vals[ORC_C][c] = Cf ? (double)Cf[c * n + p] : Cd[c * n + p];
-            vals[ORC_F][c] = Ff ? (double)Ff[c * n + p] : Fd[c * n + p];
-        }
+        for (int c = 0; c < dim * dim; ++c) vals[ORC_C][c] = Cf ? (double)Cf[c * n + p] : Cd[c * n + p];
+        for (int c = 0; c < nc3; ++c) vals[ORC_F][c] = Ff ? (double)Ff[c * n + p] : Fd[c * n + p];
         encode_record(s, (const double(*)[9])vals, (uint32_t)p, step, tag, rec, W, stats);
         for (int w = 0; w < W; ++w) words[(int64_t)w * n + p] = rec[w];
     }
@@ -376,7 +387,7 @@ int orc_decode(const orc_scheme *s, int64_t n, const uint32_t *words,
 {
     int32_t W;
     if (orc_layout(s, 0, 0, 0, &W)) return -1;
-    int dim = s->dim;
+    int dim = s->dim, nc3 = nc3_of(s);
     uint32_t rec[32];
     for (int64_t p = 0; p < n; ++p) {
         for (int w = 0; w < W; ++w) rec[w] = words[(int64_t)w * n + p];
@@ -386,10 +397,10 @@ int orc_decode(const orc_scheme *s, int64_t n, const uint32_t *words,
             if (x) x[c * n + p] = vals[ORC_X][c];
             if (v) v[c * n + p] = vals[ORC_V][c];
         }
-        for (int c = 0; c < dim * dim; ++c) {
+        for (int c = 0; c < dim * dim; ++c)
             if (C) C[c * n + p] = vals[ORC_C][c];
+        for (int c = 0; c < nc3; ++c)
             if (F) F[c * n + p] = vals[ORC_F][c];
-        }
     }
     return 0;
 }

@@ -158,6 +158,14 @@ void orc_polar(int dim, const double *F, double *R)
 
 /* Kirchhoff stress of fixed-corotated elasticity,
  * psi = mu |F-R|^2 + lambda/2 (J-1)^2,  tau = dpsi/dF F^T. */
+/* Weakly compressible fluid: Kirchhoff stress E (J - 1) I (E the pressure
+ * coefficient; the MLS-MPM fluid of Hu et al. 2018). */
+void orc_fluid_stress(int dim, double J, double E, double *tau)
+{
+    for (int i = 0; i < dim * dim; ++i) tau[i] = 0.0;
+    for (int a = 0; a < dim; ++a) tau[a * dim + a] = E * (J - 1.0);
+}
+
 void orc_kirchhoff(int dim, const double *F, double mu, double la, double *tau)
 {
     double R[9];
@@ -217,11 +225,16 @@ int orc_p2g(const orc_params *p, int64_t n, const double *x, const double *v,
     for (int64_t q = 0; q < n; ++q) {
         double xp[3], vp[3], Cp[9], Fp[9], tau[9], A[9];
         for (int a = 0; a < dim; ++a) { xp[a] = x[a * n + q]; vp[a] = v[a * n + q]; }
-        for (int c = 0; c < dim * dim; ++c) { Cp[c] = C[c * n + q]; Fp[c] = F[c * n + q]; }
+        for (int c = 0; c < dim * dim; ++c) Cp[c] = C[c * n + q];
         int base[3];
         double fx[3], w[3][3];
         stencil(p, xp, base, fx, w);
-        orc_kirchhoff(dim, Fp, mu, la, tau);
+        if (p->material == ORC_FLUID) {
+            orc_fluid_stress(dim, F[q], p->E, tau);
+        } else {
+            for (int c = 0; c < dim * dim; ++c) Fp[c] = F[c * n + q];
+            orc_kirchhoff(dim, Fp, mu, la, tau);
+        }
         for (int c = 0; c < dim * dim; ++c)
             A[c] = -p->dt * p->p_vol * 4.0 * inv_dx * inv_dx * tau[c] + p_mass * Cp[c];
         for (int s = 0; s < nst; ++s) {
@@ -301,7 +314,12 @@ int orc_g2p(const orc_params *p, int64_t n, const double *x, const double *F,
         }
         for (int c = 0; c < dim * dim; ++c)
             if (C_new) C_new[c * n + q] = nC[c];
-        if (F_new) {
+        if (F_new && p->material == ORC_FLUID) {
+            /* volume ratio: J' = J (1 + dt tr C') */
+            double tr = 0.0;
+            for (int a = 0; a < dim; ++a) tr += nC[a * dim + a];
+            F_new[q] = F[q] * (1.0 + p->dt * tr);
+        } else if (F_new) {
             for (int i = 0; i < dim; ++i)
                 for (int j = 0; j < dim; ++j) {
                     double acc = 0.0;
@@ -390,6 +408,9 @@ orc_sim *orc_sim_new(const orc_scheme *s, const orc_params *p, int64_t n, const 
     int32_t W;
     if (orc_layout(s, 0, 0, 0, &W)) return 0;
     if (p->dim != s->dim || p->grid_res < 4) return 0;
+    int has_j = 0;
+    for (int i = 0; i < 4; ++i) has_j |= s->f[i].field == ORC_J;
+    if (has_j != (p->material == ORC_FLUID)) return 0;
     orc_sim *sim = (orc_sim *)calloc(1, sizeof(orc_sim));
     sim->s = *s;
     sim->p = *p;

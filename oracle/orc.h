@@ -22,15 +22,20 @@
 extern "C" {
 #endif
 
-/* Particle attributes quantized in the MPM example of the paper
- * (Sec. 3.1, Fig. 3): position, velocity, affine velocity C, deformation
- * gradient F. */
-enum { ORC_X = 0, ORC_V = 1, ORC_C = 2, ORC_F = 3 };
+/* Particle attributes quantized in the MPM examples of the paper
+ * (Sec. 3.1, Fig. 3; Sec. 8.3): position, velocity, affine velocity C, and
+ * either the deformation gradient F (elastic solid) or the volume ratio J
+ * (fluid).  F and J share the fourth state slot: arrays passed for "F"
+ * hold J (one row) for a fluid. */
+enum { ORC_X = 0, ORC_V = 1, ORC_C = 2, ORC_F = 3, ORC_J = 4 };
+/* Materials: fixed-corotated elastic solid (F), weakly compressible fluid (J)
+ * with Kirchhoff stress E (J - 1) I, E the pressure coefficient. */
+enum { ORC_ELASTIC = 0, ORC_FLUID = 1 };
 /* Storage kinds: fixed point (Eq. 3), shared-exponent float, raw float32. */
 enum { ORC_FIXED = 0, ORC_SHARED_EXP = 1, ORC_RAW_F32 = 2 };
 
 typedef struct {
-    int32_t field;        /* ORC_X .. ORC_F */
+    int32_t field;        /* ORC_X .. ORC_J */
     int32_t kind;         /* ORC_FIXED / ORC_SHARED_EXP / ORC_RAW_F32 */
     int32_t bits;         /* bits per component (SHARED_EXP: sign + magnitude) */
     int32_t exp_bits;     /* SHARED_EXP only: width of the shared exponent */
@@ -49,6 +54,7 @@ typedef struct {
 typedef struct {
     int32_t dim, grid_res, bound_cells, sort_every;
     double dt, gravity[3], E, nu, rho, p_vol;
+    int32_t material, pad;   /* ORC_ELASTIC / ORC_FLUID */
 } orc_params;
 
 /* Per-field statistics: saturations, NaN inputs, round-ups, round-downs. */
@@ -71,6 +77,7 @@ int  orc_validate(const orc_scheme *s);
 /* ---- MLS-MPM (mpm.c) ---- */
 void orc_polar(int dim, const double *F, double *R);
 void orc_kirchhoff(int dim, const double *F, double mu, double la, double *tau);
+void orc_fluid_stress(int dim, double J, double E, double *tau);
 int  orc_p2g(const orc_params *p, int64_t n, const double *x, const double *v,
              const double *C, const double *F, double *grid_m, double *grid_mom);
 int  orc_grid_update(const orc_params *p, double *grid_m, double *grid_mom);
@@ -79,7 +86,8 @@ int  orc_g2p(const orc_params *p, int64_t n, const double *x, const double *F,
              double *F_new);
 int  orc_sort_order(const orc_params *p, int64_t n, const double *x, int64_t *order);
 
-/* ---- adjoint (adjoint.c): state = x[d][n], v[d][n], C[d*d][n], F[d*d][n] ---- */
+/* ---- adjoint (adjoint.c): state = x[d][n], v[d][n], C[d*d][n], F[d*d][n]
+ * (fluid: J[1][n] in place of F) ---- */
 int  orc_step_exact(const orc_params *p, int64_t n, const double *in, double *out);
 int  orc_step_vjp(const orc_params *p, int64_t n, const double *in, const double *lam_out,
                   double *lam_in);

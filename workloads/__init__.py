@@ -77,15 +77,34 @@ def scheme_c3(seed=0):
         fixed("F", 14, -1.0, 1.0, True, rel_identity=True)]}
 
 
+def scheme_fluid(dim=2, dither=False, seed=0):
+    """Fluid state x, v, C, J (Sec. 8.3: position, velocity, volume ratio,
+    affine velocity): x 20-bit, v 16-bit in [-20, 20], C 16-bit shared
+    exponent (|C| < 2048; the paper widens C's range for its fluid), J 16-bit
+    stored as J - 1 in [-0.5, 0.5]."""
+    return {"dim": dim, "seed": seed, "fields": [
+        fixed("x", 20, 0.0, 1.0, dither),
+        fixed("v", 16, -20.0, 20.0, dither),
+        shared_exp("C", 16, 6, 2048.0, dither),
+        fixed("J", 16, -0.5, 0.5, dither, rel_identity=True)]}
+
+
+def scheme_fluid_fp32(dim=2, seed=0):
+    return {"dim": dim, "seed": seed, "fields": [raw("x"), raw("v"), raw("C"), raw("J")]}
+
+
 def scheme_fp32(dim=3, seed=0):
     return {"dim": dim, "seed": seed, "fields": [raw("x"), raw("v"), raw("C"), raw("F")]}
 
 
-def params(dim, grid_res, dt, p_vol, sort_every=0, bound_cells=3, gravity=-9.8):
+def params(dim, grid_res, dt, p_vol, sort_every=0, bound_cells=3, gravity=-9.8, material="elastic", E=None):
     g = [0.0, gravity, 0.0][:3]
     return {"dim": dim, "grid_res": grid_res, "bound_cells": bound_cells,
-            "sort_every": sort_every, "dt": dt, "gravity": g, "E": E_MODULUS,
-            "nu": POISSON, "rho": DENSITY, "p_vol": p_vol}
+            "sort_every": sort_every, "dt": dt, "gravity": g, "E": E_MODULUS if E is None else E,
+            "nu": POISSON, "rho": DENSITY, "p_vol": p_vol, "material": material}
+
+
+FLUID_E = 400.0  # pressure coefficient of the fluid scenes
 
 
 def rest_state(dim, n):
@@ -180,6 +199,26 @@ def c5(seed=0, grid_res=64, steps=64):
     return {"name": "c5", "scheme": sc, "steps": steps, "n": n,
             "params": params(3, grid_res, 2e-4, side ** 3 / n, sort_every=0),
             "state": (x, v, C, F)}
+
+
+def dam_break(dim=2, seed=0, grid_res=128, ppc=4, steps=100, dither=False, sort_every=10):
+    """Fluid dam break (Sec. 8.1): a column of fluid at rest in the corner,
+    [0.1, 0.4] x [0.1, 0.6] (x [0.3, 0.7] in z), ppc particles per cell,
+    J = 1, pressure coefficient 400, dt = 1e-4 (2D) / 5e-5 (3D)."""
+    rng = np.random.default_rng([seed, 7])
+    lo = np.array([0.1, 0.1, 0.3])[:dim]
+    hi = np.array([0.4, 0.6, 0.7])[:dim]
+    cells = np.prod((hi - lo) * grid_res)
+    n = int(round(cells * ppc))
+    x = (lo[:, None] + (hi - lo)[:, None] * rng.random((dim, n))).astype(np.float32)
+    v = np.zeros((dim, n), dtype=np.float32)
+    C = np.zeros((dim * dim, n), dtype=np.float32)
+    J = np.ones((1, n), dtype=np.float32)
+    dt = 1e-4 if dim == 2 else 5e-5
+    vol = float(np.prod(hi - lo))
+    return {"name": f"dam{dim}d", "scheme": scheme_fluid(dim, dither, seed), "steps": steps, "n": n,
+            "params": params(dim, grid_res, dt, vol / n, sort_every=sort_every, material="fluid", E=FLUID_E),
+            "state": (x, v, C, J)}
 
 
 def c4_scene(stream_seed, index, steps=100, n_max=2 ** 21, materialize=True):
