@@ -49,8 +49,18 @@ typedef enum {
     MPMQ_ENOTIMPL = -5
 } mpmq_status;
 
-/* Particle attributes (Sec. 3.1, Fig. 3). */
-typedef enum { MPMQ_FIELD_X = 0, MPMQ_FIELD_V = 1, MPMQ_FIELD_C = 2, MPMQ_FIELD_F = 3 } mpmq_field;
+/* Particle attributes (Sec. 3.1, Fig. 3; Sec. 8.3): position, velocity,
+ * affine velocity C, and either the deformation gradient F (elastic solid)
+ * or the volume ratio J (fluid).  F and J share the fourth state slot: the
+ * arrays, statistics and adjoint rows named F hold J (one component) for a
+ * fluid. */
+typedef enum { MPMQ_FIELD_X = 0, MPMQ_FIELD_V = 1, MPMQ_FIELD_C = 2, MPMQ_FIELD_F = 3, MPMQ_FIELD_J = 4 } mpmq_field;
+
+/* Materials.  MPMQ_ELASTIC: fixed-corotated solid, state x, v, C, F.
+ * MPMQ_FLUID: weakly compressible fluid (the MLS-MPM fluid of Hu et al.
+ * 2018): Kirchhoff stress E (J - 1) I with E the pressure coefficient,
+ * J' = J (1 + dt tr C'); state x, v, C, J. */
+typedef enum { MPMQ_ELASTIC = 0, MPMQ_FLUID = 1 } mpmq_material;
 
 /* Storage kinds.
  * MPMQ_FIXED      Eq. 3 over [lo, hi): Delta = (hi-lo) 2^-bits,
@@ -69,7 +79,7 @@ typedef enum { MPMQ_FIELD_X = 0, MPMQ_FIELD_V = 1, MPMQ_FIELD_C = 2, MPMQ_FIELD_
 typedef enum { MPMQ_FIXED = 0, MPMQ_SHARED_EXP = 1, MPMQ_RAW_F32 = 2 } mpmq_kind;
 
 /* flags of mpmq_field_scheme */
-#define MPMQ_REL_IDENTITY 1 /* F only: store F - I (diagonal in [lo+1, hi+1)) */
+#define MPMQ_REL_IDENTITY 1 /* F or J only: store F - I / J - 1 (diagonal in [lo+1, hi+1)) */
 
 typedef struct {
     int32_t field;    /* mpmq_field */
@@ -83,14 +93,15 @@ typedef struct {
 
 typedef struct {
     int32_t dim;                      /* 2 or 3 */
-    int32_t n_fields;                 /* 4: X, V, C, F each exactly once */
+    int32_t n_fields;                 /* 4: X, V, C and one of F / J, each once */
     const mpmq_field_scheme *fields;  /* array order = bit placement order */
     uint64_t seed;                    /* Philox key (low word, high word) */
 } mpmq_scheme;
 
 /* MLS-MPM parameters.  Domain [0,1)^dim, grid_res nodes per axis
  * (dx = 1/grid_res, 8 <= grid_res <= 1024), quadratic B-splines,
- * fixed-corotated elasticity with Young's modulus E and Poisson ratio nu,
+ * fixed-corotated elasticity with Young's modulus E and Poisson ratio nu
+ * (MPMQ_FLUID: E is the pressure coefficient, nu unused),
  * particle mass rho*p_vol.  Within bound_cells nodes of a wall the grid
  * velocity component pointing into the wall is zeroed.  Particles are
  * re-sorted by cell at every step s with s % sort_every == 0
@@ -98,6 +109,8 @@ typedef struct {
 typedef struct {
     int32_t dim, grid_res, bound_cells, sort_every;
     double dt, gravity[3], E, nu, rho, p_vol;
+    int32_t material;  /* mpmq_material; must match the scheme (F: ELASTIC, J: FLUID) */
+    int32_t reserved;  /* 0 */
 } mpmq_params;
 
 typedef struct {
@@ -149,7 +162,8 @@ mpmq_status mpmq_destroy(mpmq_ctx *ctx);
 
 /* Encodes n particles (0 <= n <= capacity) from float32 device arrays in
  * component-major structure-of-arrays layout: x[c*n+p] (c < dim),
- * v[c*n+p], C[(i*dim+j)*n+p], F[(i*dim+j)*n+p] (full F, row-major).
+ * v[c*n+p], C[(i*dim+j)*n+p], F[(i*dim+j)*n+p] (full F, row-major; a
+ * fluid passes J[p] there).
  * Dithered fields use Philox counter (p, step_count, group, 2).  Marks the
  * state unsorted (the next step sorts) and resets ids to 0..n-1. */
 mpmq_status mpmq_encode(mpmq_ctx *ctx, const float *x, const float *v, const float *C,

@@ -21,7 +21,13 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmq.so")
 
-FIELDS = {"x": 0, "v": 1, "C": 2, "F": 3}
+FIELDS = {"x": 0, "v": 1, "C": 2, "F": 3, "J": 4}
+MATERIALS = {"elastic": 0, "fluid": 1}
+
+
+def slot3_name(scheme: dict) -> str:
+    """The field in the fourth state slot: "F" (elastic solid) or "J" (fluid)."""
+    return "J" if any(f["field"] == "J" for f in scheme["fields"]) else "F"
 KINDS = {"fixed": 0, "shared_exp": 1, "raw_f32": 2}
 REL_IDENTITY = 1
 
@@ -49,7 +55,8 @@ class mpmq_scheme(ct.Structure):
 class mpmq_params(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("grid_res", ct.c_int32), ("bound_cells", ct.c_int32),
                 ("sort_every", ct.c_int32), ("dt", ct.c_double), ("gravity", ct.c_double * 3),
-                ("E", ct.c_double), ("nu", ct.c_double), ("rho", ct.c_double), ("p_vol", ct.c_double)]
+                ("E", ct.c_double), ("nu", ct.c_double), ("rho", ct.c_double), ("p_vol", ct.c_double),
+                ("material", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class mpmq_sizes(ct.Structure):
@@ -195,6 +202,8 @@ def make_params(params: dict):
     p.nu = params["nu"]
     p.rho = params["rho"]
     p.p_vol = params["p_vol"]
+    p.material = MATERIALS[params.get("material", "elastic")]
+    p.reserved = 0
     return p
 
 
@@ -219,6 +228,8 @@ class Context:
         L = load()
         self.scheme, self.params = scheme, params
         self.dim = scheme["dim"]
+        self.f3 = slot3_name(scheme)
+        self.nc3 = 1 if self.f3 == "J" else self.dim * self.dim
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.sizes = mpmq_query_sizes(scheme, params, capacity)
@@ -248,7 +259,8 @@ class Context:
 
     # -- C ABI calls ----------------------------------------------------------
     def encode(self, x, v, C, F):
-        """x, v: [dim, n]; C, F: [dim*dim, n] float32 CUDA tensors (contiguous)."""
+        """x, v: [dim, n]; C: [dim*dim, n]; F: [dim*dim, n] (fluid: J [1, n])
+        float32 CUDA tensors (contiguous)."""
         import torch
         ts = [t.to(device=self.device, dtype=torch.float32).contiguous() for t in (x, v, C, F)]
         n = ts[0].shape[-1]
@@ -259,7 +271,7 @@ class Context:
     def decode(self):
         import torch
         d, n = self.dim, self.n
-        out = [torch.empty((k, n), dtype=torch.float32, device=self.device) for k in (d, d, d * d, d * d)]
+        out = [torch.empty((k, n), dtype=torch.float32, device=self.device) for k in (d, d, d * d, self.nc3)]
         _check(load().mpmq_decode(self._h, *[t.data_ptr() for t in out]), self._h)
         return tuple(out)
 
@@ -295,7 +307,7 @@ class Context:
     def stats(self):
         st = mpmq_stats_t()
         _check(load().mpmq_stats(self._h, ct.byref(st)), self._h)
-        names = ["x", "v", "C", "F"]
+        names = ["x", "v", "C", self.f3]
         out = {names[i]: {"sat": st.sat[i], "nan": st.nan[i], "up": st.up[i], "down": st.down[i]}
                for i in range(4)}
         out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes)
@@ -341,12 +353,12 @@ class Context:
         L = load()
         _check(L.mpmq_adjoint_workspace(self._h, ct.byref(s), ct.byref(b)), self._h)
         ws = torch.empty(max(int(b.value), 256), dtype=torch.uint8, device=self.device)
-        rows = 2 * self.dim + 2 * self.dim * self.dim
+        rows = 2 * self.dim + self.dim * self.dim + self.nc3
         lam0 = torch.empty((rows, self.n), dtype=torch.float32, device=self.device) if want_lambda0 else None
         res = mpmq_adjoint_result()
         _check(L.mpmq_adjoint(self._h, ct.byref(s), ct.c_void_p(ws.data_ptr()), int(b.value),
                               ct.c_void_p(lam0.data_ptr()) if lam0 is not None else None, ct.byref(res)), self._h)
-        names = ["x", "v", "C", "F"]
+        names = ["x", "v", "C", self.f3]
         out = {"z": res.z, "G": {names[i]: res.G[i] for i in range(4)}, "g": {names[i]: res.g[i] for i in range(4)},
                "lo": {names[i]: res.lo[i] for i in range(4)}, "hi": {names[i]: res.hi[i] for i in range(4)},
                "recomputed": res.recomputed, "states": res.states, "workspace_bytes": b.value}
@@ -391,8 +403,8 @@ def auto_scheme(base: dict, adjoint_result: dict, n: int, mode="error", eps=1e-3
     `range_factor` about its centre, and the bits of mpmq_solve_scheme.
     Placement order, dither, REL_IDENTITY and the seed follow `base`."""
     dim = base["dim"]
-    names = ["x", "v", "C", "F"]
-    ncomp = {"x": dim, "v": dim, "C": dim * dim, "F": dim * dim}
+    names = ["x", "v", "C", slot3_name(base)]
+    ncomp = {"x": dim, "v": dim, "C": dim * dim, "F": dim * dim, "J": 1}
     lo, hi = {}, {}
     for f in names:
         mid = 0.5 * (adjoint_result["lo"][f] + adjoint_result["hi"][f])
@@ -439,6 +451,7 @@ class QuantizedRollout:
                     d = handle.dim
                     lam = res["lambda0"]
                     fctx.save_for_backward(lam[:d], lam[d:2 * d], lam[2 * d:2 * d + d * d], lam[2 * d + d * d:])
+                    # (the last block has handle.nc3 rows: F, or J for a fluid)
                     return torch.tensor(res["z"], dtype=torch.float64, device=x.device)
 
                 @staticmethod

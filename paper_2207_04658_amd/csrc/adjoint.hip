@@ -12,7 +12,7 @@
 
 namespace mpmq {
 
-template <int DIM> constexpr int LROWS() { return 2 * DIM + 2 * DIM * DIM; }
+template <int DIM, int MAT> constexpr int LROWS() { return 2 * DIM + DIM * DIM + nc3<DIM, MAT>(); }
 
 // d w / d x_a for a node with offsets o: inv_dx N'_{o_a}(f_a) prod_{b!=a} N_{o_b}(f_b)
 __device__ __forceinline__ void bspline_d(float f, float inv_dx, float *dw) {
@@ -156,20 +156,20 @@ __device__ __forceinline__ void stencil_all(const DevParams &P, const double *xd
 
 // G2P backward: from lambda_{t+1} (of x', v', C', F') to the partial lambda_t
 // of x and F, and the node adjoints lambda_v_i (scattered with atomics).
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sch, DevParams P,
                                                 const uint32_t *__restrict__ words, int64_t cap, int64_t n,
                                                 const GNode *__restrict__ grid, const float *__restrict__ lin,
                                                 float *__restrict__ lout, float4 *__restrict__ nadj) {
-    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST;
+    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST, N3 = nc3<DIM, MAT>();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p >= n) return;
     SchemeRef s = scheme_ref(sch);
     const uint32_t p4 = (uint32_t)p * 4u;
     double xd[DIM];
-    float F[D2];
+    float F[N3];
     dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
-    dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+    dec_field<DIM, fid3<MAT>(), float>(&s->f[3], words, cap, p4, F);
     int base[DIM];
     float fx[DIM], w[DIM][3], dw[DIM][3];
     stencil_all<DIM>(P, xd, base, fx, w, dw);
@@ -196,32 +196,41 @@ __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sc
 #pragma unroll
             for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] += D * wt * vi[a] * d[b];
     }
-    float lx[DIM], lv[DIM], lC[D2], lF[D2], oF[D2];
+    float lx[DIM], lv[DIM], lC[D2], lF[N3], oF[N3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         lx[a] = lin[a * n + p];
         lv[a] = lin[(DIM + a) * n + p];
     }
 #pragma unroll
-    for (int c = 0; c < D2; ++c) {
-        lC[c] = lin[(2 * DIM + c) * n + p];
-        lF[c] = lin[(2 * DIM + D2 + c) * n + p];
-    }
-    // F' = (I + dt C') F
+    for (int c = 0; c < D2; ++c) lC[c] = lin[(2 * DIM + c) * n + p];
 #pragma unroll
-    for (int i = 0; i < DIM; ++i)
+    for (int c = 0; c < N3; ++c) lF[c] = lin[(2 * DIM + D2 + c) * n + p];
+    if constexpr (MAT == 1) {
+        // J' = J (1 + dt tr C')
+        float tr = 0.0f;
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-            float aF = 0.0f, aC = 0.0f;
+        for (int a = 0; a < DIM; ++a) tr += Cn[a * DIM + a];
+        oF[0] = lF[0] * (1.0f + P.dt * tr);
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                const float Mki = ((k == i) ? 1.0f : 0.0f) + P.dt * Cn[k * DIM + i];
-                aF += Mki * lF[k * DIM + j];
-                aC += lF[i * DIM + k] * F[j * DIM + k];
+        for (int a = 0; a < DIM; ++a) lC[a * DIM + a] += lF[0] * F[0] * P.dt;
+    } else {
+        // F' = (I + dt C') F
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                float aF = 0.0f, aC = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    const float Mki = ((k == i) ? 1.0f : 0.0f) + P.dt * Cn[k * DIM + i];
+                    aF += Mki * lF[k * DIM + j];
+                    aC += lF[i * DIM + k] * F[j * DIM + k];
+                }
+                oF[i * DIM + j] = aF;
+                lC[i * DIM + j] += P.dt * aC;
             }
-            oF[i * DIM + j] = aF;
-            lC[i * DIM + j] += P.dt * aC;
-        }
+    }
     // x' = x + dt v'
     float ox[DIM];
 #pragma unroll
@@ -271,10 +280,9 @@ __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sc
         lout[(DIM + a) * n + p] = 0.0f;
     }
 #pragma unroll
-    for (int c = 0; c < D2; ++c) {
-        lout[(2 * DIM + c) * n + p] = 0.0f;
-        lout[(2 * DIM + D2 + c) * n + p] = oF[c];
-    }
+    for (int c = 0; c < D2; ++c) lout[(2 * DIM + c) * n + p] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < N3; ++c) lout[(2 * DIM + D2 + c) * n + p] = oF[c];
 }
 
 // Grid backward: v_i = mom_i / m_i + dt g (components zeroed by the wall
@@ -316,40 +324,46 @@ __global__ __launch_bounds__(WG) void k_adj_grid(DevParams P, const GNode *__res
 
 // P2G backward: gathers (lambda_mom_i, lambda_m_i) and adds the partial
 // lambda_t of x, v, C and F (stress through its VJP).
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_p2g(const DevScheme *__restrict__ sch, DevParams P,
                                                 const uint32_t *__restrict__ words, int64_t cap, int64_t n,
                                                 const float4 *__restrict__ nadj, float *__restrict__ lout) {
-    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST;
+    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST, N3 = nc3<DIM, MAT>();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p >= n) return;
     SchemeRef s = scheme_ref(sch);
     const uint32_t p4 = (uint32_t)p * 4u;
     double xd[DIM];
-    float v[DIM], C[D2], F[D2];
+    float v[DIM], C[D2], F[N3];
     dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
     dec_field<DIM, 1, float>(&s->f[1], words, cap, p4, v);
     dec_field<DIM, 2, float>(&s->f[2], words, cap, p4, C);
-    dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+    dec_field<DIM, fid3<MAT>(), float>(&s->f[3], words, cap, p4, F);
     int base[DIM];
     float fx[DIM], w[DIM][3], dw[DIM][3];
     stencil_all<DIM>(P, xd, base, fx, w, dw);
     // A = -dt V D tau + m C  (physical units: p_mass * (stress_over_m tau + C))
-    float R[D2];
-    if constexpr (DIM == 2) polar2(F, R);
-    else polar3(F, R);
-    const float J = det_f<DIM>(F);
     float A[D2];
+    if constexpr (MAT == 1) {
+        const float t = P.pc * (F[0] - 1.0f);  // fluid: tau = pc (J - 1) I
 #pragma unroll
-    for (int i = 0; i < DIM; ++i)
+        for (int i = 0; i < D2; ++i) A[i] = P.p_mass * (((i % (DIM + 1) == 0) ? P.stress_over_m * t : 0.0f) + C[i]);
+    } else {
+        float R[D2];
+        if constexpr (DIM == 2) polar2(F, R);
+        else polar3(F, R);
+        const float J = det_f<DIM>(F);
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-            float t = 0.0f;
+        for (int i = 0; i < DIM; ++i)
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
-            t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
-            A[i * DIM + j] = P.p_mass * (P.stress_over_m * t + C[i * DIM + j]);
-        }
+            for (int j = 0; j < DIM; ++j) {
+                float t = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
+                t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
+                A[i * DIM + j] = P.p_mass * (P.stress_over_m * t + C[i * DIM + j]);
+            }
+    }
     const float m = P.p_mass;
     float lx[DIM], lv[DIM], lA[D2];
 #pragma unroll
@@ -394,33 +408,38 @@ __global__ __launch_bounds__(WG) void k_adj_p2g(const DevScheme *__restrict__ sc
         for (int a = 0; a < DIM; ++a) lx[a] += gw[a] * lw;
     }
     // A = p_mass stress_over_m tau + p_mass C
-    float lt[D2], lF[D2];
+    float lt[D2], lF[N3];
 #pragma unroll
-    for (int c = 0; c < D2; ++c) {
-        lt[c] = P.p_mass * P.stress_over_m * lA[c];
-        lF[c] = 0.0f;
+    for (int c = 0; c < D2; ++c) lt[c] = P.p_mass * P.stress_over_m * lA[c];
+#pragma unroll
+    for (int c = 0; c < N3; ++c) lF[c] = 0.0f;
+    if constexpr (MAT == 1) {
+        float tr = 0.0f;  // tau = pc (J - 1) I
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) tr += lt[a * DIM + a];
+        lF[0] = P.pc * tr;
+    } else {
+        stress_vjp<DIM>(P, F, lt, lF);
     }
-    stress_vjp<DIM>(P, F, lt, lF);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         lout[a * n + p] += lx[a];
         lout[(DIM + a) * n + p] += lv[a];
     }
 #pragma unroll
-    for (int c = 0; c < D2; ++c) {
-        lout[(2 * DIM + c) * n + p] += m * lA[c];
-        lout[(2 * DIM + D2 + c) * n + p] += lF[c];
-    }
+    for (int c = 0; c < D2; ++c) lout[(2 * DIM + c) * n + p] += m * lA[c];
+#pragma unroll
+    for (int c = 0; c < N3; ++c) lout[(2 * DIM + D2 + c) * n + p] += lF[c];
 }
 
 // Objective at the final state: 0 = centre of mass along `axis`, 1 = kinetic
 // energy.  Writes lambda_T and accumulates z (binary64) into acc[0].
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_objective(const DevScheme *__restrict__ sch, DevParams P,
                                                       const uint32_t *__restrict__ words, int64_t cap, int64_t n,
                                                       int objective, int axis, float *__restrict__ lout,
                                                       double *__restrict__ acc) {
-    constexpr int LR = LROWS<DIM>();
+    constexpr int LR = LROWS<DIM, MAT>();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     double zc = 0.0;
     if (p < n) {
@@ -449,10 +468,10 @@ __global__ __launch_bounds__(WG) void k_adj_objective(const DevScheme *__restric
 }
 
 // G[f] += sum lambda, g[f] += sum lambda^2 over the rows of field f.
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_reduce(const float *__restrict__ lam, int64_t n,
                                                    double *__restrict__ acc) {
-    constexpr int LR = LROWS<DIM>();
+    constexpr int LR = LROWS<DIM, MAT>();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     double G[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0};
     if (p < n) {
@@ -495,24 +514,24 @@ __device__ __forceinline__ uint32_t ord_key(float f) {
 // Per-field minimum and maximum of the stored (decoded) values, F - I for a
 // REL_IDENTITY F:
 // rng[f] = min key, rng[4 + f] = max key (ord_key order).
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ sch, const uint32_t *__restrict__ words,
                                                   int64_t cap, int64_t n, uint32_t *__restrict__ rng) {
-    constexpr int D2 = DIM * DIM;
+    constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     uint32_t lo[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[4] = {0u, 0u, 0u, 0u};
     if (p < n) {
         SchemeRef s = scheme_ref(sch);
         const uint32_t p4 = (uint32_t)p * 4u;
         double xd[DIM];
-        float v[DIM], C[D2], F[D2];
+        float v[DIM], C[D2], F[N3];
         dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xd);
         dec_field<DIM, 1, float>(&s->f[1], words, cap, p4, v);
         dec_field<DIM, 2, float>(&s->f[2], words, cap, p4, C);
-        dec_field<DIM, 3, float>(&s->f[3], words, cap, p4, F);
+        dec_field<DIM, fid3<MAT>(), float>(&s->f[3], words, cap, p4, F);
         if (s->f[3].rel) {
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) F[a * (DIM + 1)] -= 1.0f;
+            for (int c = 0; c < N3; c += DIM + 1) F[c] -= 1.0f;
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -522,8 +541,12 @@ __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ 
         }
 #pragma unroll
         for (int c = 0; c < D2; ++c) {
-            const uint32_t kc = ord_key(C[c]), kf = ord_key(F[c]);
+            const uint32_t kc = ord_key(C[c]);
             lo[2] = min(lo[2], kc); hi[2] = max(hi[2], kc);
+        }
+#pragma unroll
+        for (int c = 0; c < N3; ++c) {
+            const uint32_t kf = ord_key(F[c]);
             lo[3] = min(lo[3], kf); hi[3] = max(hi[3], kf);
         }
     }
@@ -557,43 +580,42 @@ __global__ void k_adj_unpermute(const float *__restrict__ lam, const uint32_t *_
 
 static dim3 agrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
 
-hipError_t launch_adj_objective(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
-                                int64_t n, int objective, int axis, float *lam, double *acc, hipStream_t st) {
-    if (dim == 3)
-        hipLaunchKernelGGL(k_adj_objective<3>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, objective, axis, lam, acc);
-    else
-        hipLaunchKernelGGL(k_adj_objective<2>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, objective, axis, lam, acc);
+#define MPMQ_ADJ_DISPATCH(KERNEL, GRID, ...)                                                              \
+    do {                                                                                                 \
+        if (dim == 3 && mat) hipLaunchKernelGGL((KERNEL<3, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);     \
+        else if (dim == 3) hipLaunchKernelGGL((KERNEL<3, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);       \
+        else if (mat) hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);            \
+        else hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);                     \
+    } while (0)
+
+hipError_t launch_adj_objective(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words,
+                                int64_t cap, int64_t n, int objective, int axis, float *lam, double *acc,
+                                hipStream_t st) {
+    MPMQ_ADJ_DISPATCH(k_adj_objective, agrid(n), s, P, words, cap, n, objective, axis, lam, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_step(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
-                           int64_t n, const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
-                           hipStream_t st) {
+hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words,
+                           int64_t cap, int64_t n, const GNode *grid, int64_t nodes, const float *lin, float *lout,
+                           float4 *nadj, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_f4, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 65536)), dim3(256), 0, st,
                        nadj, nodes);
-    if (dim == 3) {
-        hipLaunchKernelGGL(k_adj_g2p<3>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, grid, lin, lout, nadj);
-        hipLaunchKernelGGL(k_adj_grid<3>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
-        hipLaunchKernelGGL(k_adj_p2g<3>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, nadj, lout);
-    } else {
-        hipLaunchKernelGGL(k_adj_g2p<2>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, grid, lin, lout, nadj);
-        hipLaunchKernelGGL(k_adj_grid<2>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
-        hipLaunchKernelGGL(k_adj_p2g<2>, agrid(n), dim3(WG), 0, st, s, P, words, cap, n, nadj, lout);
-    }
+    MPMQ_ADJ_DISPATCH(k_adj_g2p, agrid(n), s, P, words, cap, n, grid, lin, lout, nadj);
+    if (dim == 3) hipLaunchKernelGGL(k_adj_grid<3>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
+    else hipLaunchKernelGGL(k_adj_grid<2>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
+    MPMQ_ADJ_DISPATCH(k_adj_p2g, agrid(n), s, P, words, cap, n, nadj, lout);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_reduce(int dim, const float *lam, int64_t n, double *acc, hipStream_t st) {
-    if (dim == 3) hipLaunchKernelGGL(k_adj_reduce<3>, agrid(n), dim3(WG), 0, st, lam, n, acc);
-    else hipLaunchKernelGGL(k_adj_reduce<2>, agrid(n), dim3(WG), 0, st, lam, n, acc);
+hipError_t launch_adj_reduce(int dim, int mat, const float *lam, int64_t n, double *acc, hipStream_t st) {
+    MPMQ_ADJ_DISPATCH(k_adj_reduce, agrid(n), lam, n, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_range(int dim, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n, uint32_t *rng,
-                            hipStream_t st) {
+hipError_t launch_adj_range(int dim, int mat, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n,
+                            uint32_t *rng, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (dim == 3) hipLaunchKernelGGL(k_adj_range<3>, agrid(n), dim3(WG), 0, st, s, words, cap, n, rng);
-    else hipLaunchKernelGGL(k_adj_range<2>, agrid(n), dim3(WG), 0, st, s, words, cap, n, rng);
+    MPMQ_ADJ_DISPATCH(k_adj_range, agrid(n), s, words, cap, n, rng);
     return hipGetLastError();
 }
 

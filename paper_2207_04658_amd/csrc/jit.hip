@@ -39,7 +39,7 @@ std::string hexd(double v) {
 std::string initializer(const DevScheme &d) {
     std::string s = "{" + std::to_string(d.dim) + ", " + std::to_string(d.W) + ", 0u, 0u, " +
                     std::to_string(d.dither_groups) + "u, {";
-    for (int i = 0; i < 4; ++i) s += std::to_string(d.order[i]) + (i < 3 ? ", " : "}, {0, 0, 0}, {");
+    for (int i = 0; i < 4; ++i) s += std::to_string(d.order[i]) + (i < 3 ? ", " : "}, " + std::to_string(d.mat) + ", {0, 0}, {");
     for (int i = 0; i < 4; ++i) {
         const DevField &f = d.f[i];
         s += "{" + std::to_string(f.kind) + ", " + std::to_string(f.bits) + ", " + std::to_string(f.exp_bits) + ", " +
@@ -51,10 +51,11 @@ std::string initializer(const DevScheme &d) {
     return s;
 }
 
-bool compile(int dim, const std::string &init, std::vector<char> &code, std::string lowered[3], std::string *err) {
-    const std::string d = std::to_string(dim);
-    const std::string names[3] = {"mpmq::k_substep<" + d + ", false>", "mpmq::k_substep<" + d + ", true>",
-                                  "mpmq::k_p2g<" + d + ">"};
+bool compile(int dim, int mat, const std::string &init, std::vector<char> &code, std::string lowered[3],
+             std::string *err) {
+    const std::string d = std::to_string(dim), m = std::to_string(mat);
+    const std::string names[3] = {"mpmq::k_substep<" + d + ", false, " + m + ">",
+                                  "mpmq::k_substep<" + d + ", true, " + m + ">", "mpmq::k_p2g<" + d + ", " + m + ">"};
     const std::string src = "#define MPMQ_SCHEME_CONST " + init + "\n#include \"substep.hpp\"\n";
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "mpmq_specialized.hip", kJitHeaderCount, kJitHeaders,
@@ -108,7 +109,7 @@ bool jit_kernels(int dim, const DevScheme &ds, JitKernels *out, std::string *err
     }
     std::vector<char> code;
     std::string lowered[3];
-    if (!compile(dim, init, code, lowered, err)) return false;
+    if (!compile(dim, ds.mat, init, code, lowered, err)) return false;
     Entry e;
     hipError_t h = hipModuleLoadData(&e.mod, code.data());
     for (int i = 0; h == hipSuccess && i < 3; ++i) {

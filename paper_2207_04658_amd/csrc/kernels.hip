@@ -39,58 +39,58 @@ static int grid_for(int64_t n, int per_block = 256) {
 // ---------------------------------------------------------------------------
 // encode / decode (float32 SoA <-> packed words)
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_encode(const DevScheme *__restrict__ sch, const float *__restrict__ x,
                                                const float *__restrict__ v, const float *__restrict__ C,
                                                const float *__restrict__ F, int64_t n, int64_t cap,
                                                uint32_t *words, uint32_t *__restrict__ ids,
                                                uint32_t step, uint32_t tag, uint64_t *stats) {
-    constexpr int D2 = DIM * DIM;
+    constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
     LaneStats ls;
     ls.clear();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p < n) {
         double xv[DIM], qx[DIM];
-        float vv[DIM], Cv[D2], Fv[D2], qv[DIM], qC[D2], qF[D2];
+        float vv[DIM], Cv[D2], Fv[N3], qv[DIM], qC[D2], qF[N3];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             xv[c] = (double)x[c * n + p];
             vv[c] = v[c * n + p];
         }
 #pragma unroll
-        for (int c = 0; c < D2; ++c) {
-            Cv[c] = C[c * n + p];
-            Fv[c] = F[c * n + p];
-        }
+        for (int c = 0; c < D2; ++c) Cv[c] = C[c * n + p];
+#pragma unroll
+        for (int c = 0; c < N3; ++c) Fv[c] = F[c * n + p];
         Draws rnd;
         rnd.init(seed_ref(sch), (uint32_t)p, step, tag);
         OutStream os{words, cap, (uint32_t)p * 4u, 0ull, 0, 0};
-        encode_record<DIM, true>(sch, xv, vv, Cv, Fv, rnd, os, ls, qx, qv, qC, qF);
+        encode_record<DIM, true, MAT>(sch, xv, vv, Cv, Fv, rnd, os, ls, qx, qv, qC, qF);
         if (ids) ids[p] = (uint32_t)p;
     }
     flush_stats(ls, stats);
 }
 
 
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_decode(const DevScheme *__restrict__ sch, const uint32_t *__restrict__ words, int64_t n,
                                                int64_t cap, float *__restrict__ x, float *__restrict__ v,
                                                float *__restrict__ C, float *__restrict__ F) {
-    constexpr int D2 = DIM * DIM;
+    constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
     const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (p >= n) return;
-    double xv[DIM], vv[DIM], Cv[D2], Fv[D2];
-    decode_all<DIM, double>(sch, words, cap, (uint32_t)p * 4u, xv, vv, Cv, Fv);
+    double xv[DIM], vv[DIM], Cv[D2], Fv[N3];
+    decode_all<DIM, double, MAT>(sch, words, cap, (uint32_t)p * 4u, xv, vv, Cv, Fv);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         if (x) x[c * n + p] = (float)xv[c];
         if (v) v[c * n + p] = (float)vv[c];
     }
 #pragma unroll
-    for (int c = 0; c < D2; ++c) {
+    for (int c = 0; c < D2; ++c)
         if (C) C[c * n + p] = (float)Cv[c];
+#pragma unroll
+    for (int c = 0; c < N3; ++c)
         if (F) F[c * n + p] = (float)Fv[c];
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -424,26 +424,38 @@ __global__ __launch_bounds__(WG) void k_clear_touched(GNode *__restrict__ g, uin
         else hipLaunchKernelGGL((KERNEL<2>), GRID, dim3(WG), 0, st, __VA_ARGS__);                 \
     } while (0)
 
-#define MPMQ_DISPATCH2(dim, KERNEL, FLAG, GRID, ...)                                                \
-    do {                                                                                            \
-        if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, FLAG>), GRID, dim3(WG), 0, st, __VA_ARGS__);  \
-        else hipLaunchKernelGGL((KERNEL<2, FLAG>), GRID, dim3(WG), 0, st, __VA_ARGS__);             \
+// dimension x material
+#define MPMQ_DISPATCH_M(dim, mat, KERNEL, GRID, ...)                                                    \
+    do {                                                                                               \
+        if ((dim) == 3 && (mat)) hipLaunchKernelGGL((KERNEL<3, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);  \
+        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);      \
+        else if (mat) hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);             \
+        else hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);                      \
+    } while (0)
+
+// dimension x flag x material
+#define MPMQ_DISPATCH2(dim, mat, KERNEL, FLAG, GRID, ...)                                                    \
+    do {                                                                                                    \
+        if ((dim) == 3 && (mat)) hipLaunchKernelGGL((KERNEL<3, FLAG, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__); \
+        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, FLAG, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);     \
+        else if (mat) hipLaunchKernelGGL((KERNEL<2, FLAG, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);            \
+        else hipLaunchKernelGGL((KERNEL<2, FLAG, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);                     \
     } while (0)
 
 static dim3 pgrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
 
-hipError_t launch_encode(int dim, int wm, const DevScheme *s, const float *x, const float *v, const float *C,
+hipError_t launch_encode(int dim, int mat, const DevScheme *s, const float *x, const float *v, const float *C,
                          const float *F, int64_t n, int64_t cap, uint32_t *words, uint32_t *ids, uint32_t step,
                          uint32_t tag, uint64_t *stats, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    MPMQ_DISPATCH(dim, wm, k_encode, pgrid(n), s, x, v, C, F, n, cap, words, ids, step, tag, stats);
+    MPMQ_DISPATCH_M(dim, mat, k_encode, pgrid(n), s, x, v, C, F, n, cap, words, ids, step, tag, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_decode(int dim, int wm, const DevScheme *s, const uint32_t *words, int64_t n, int64_t cap,
+hipError_t launch_decode(int dim, int mat, const DevScheme *s, const uint32_t *words, int64_t n, int64_t cap,
                          float *x, float *v, float *C, float *F, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    MPMQ_DISPATCH(dim, wm, k_decode, pgrid(n), s, words, n, cap, x, v, C, F);
+    MPMQ_DISPATCH_M(dim, mat, k_decode, pgrid(n), s, words, n, cap, x, v, C, F);
     return hipGetLastError();
 }
 
@@ -518,7 +530,7 @@ hipError_t launch_items(const uint32_t *cell_start, const uint32_t *item_off, in
     return hipGetLastError();
 }
 
-hipError_t launch_p2g(int dim, int wm, const DevScheme *s, const DevParams &p, const uint32_t *words, int64_t cap,
+hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, const uint32_t *words, int64_t cap,
                       const WorkItem *items, const uint32_t *n_items, int grid, GNode *gout, uint32_t *flags_out,
                       uint64_t *stats, hipStream_t st, const JitKernels *jit) {
     if (jit && jit->p2g) {
@@ -527,7 +539,7 @@ hipError_t launch_p2g(int dim, int wm, const DevScheme *s, const DevParams &p, c
                         &stats};
         return hipModuleLaunchKernel(jit->p2g, (unsigned)grid, 1, 1, WG, 1, 1, 0, st, args, nullptr);
     }
-    MPMQ_DISPATCH(dim, wm, k_p2g, dim3(grid), s, p, words, cap, items, n_items, gout, flags_out, stats);
+    MPMQ_DISPATCH_M(dim, mat, k_p2g, dim3(grid), s, p, words, cap, items, n_items, gout, flags_out, stats);
     return hipGetLastError();
 }
 
@@ -550,7 +562,7 @@ hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblo
     return hipGetLastError();
 }
 
-hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &p, uint32_t *words, int64_t cap,
+hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams &p, uint32_t *words, int64_t cap,
                           const WorkItem *items, const uint32_t *n_items, int grid, const GNode *gcur,
                           GNode *gnxt, uint32_t *flags_nxt, uint32_t step, int do_p2g, int collect_stats,
                           int round_stats, uint64_t *stats, hipStream_t st, const JitKernels *jit) {
@@ -562,10 +574,10 @@ hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &
                                      nullptr);
     }
     if (round_stats)
-        MPMQ_DISPATCH2(dim, k_substep, true, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
+        MPMQ_DISPATCH2(dim, mat, k_substep, true, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
                        step, do_p2g, collect_stats, stats);
     else
-        MPMQ_DISPATCH2(dim, k_substep, false, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
+        MPMQ_DISPATCH2(dim, mat, k_substep, false, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
                        step, do_p2g, collect_stats, stats);
     return hipGetLastError();
 }

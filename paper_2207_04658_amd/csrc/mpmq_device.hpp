@@ -38,13 +38,19 @@ __device__ __forceinline__ SchemeRef scheme_ref(const DevScheme *p) { return (Sc
 
 
 // ---------------------------------------------------------------------------
-// Canonical component numbering x, v, C, F (matrices row-major); it fixes
-// the Philox draw of every component independently of the placement order.
+// Field ids FID: 0 x, 1 v, 2 C, 3 F, 4 J.  F and J share state slot 3 (the
+// scheme's f[3]).  Canonical component numbering x, v, C, then F or J
+// (matrices row-major); it fixes the Philox draw of every component
+// independently of the placement order.
 // ---------------------------------------------------------------------------
-template <int DIM, int FID> constexpr int ncomp() { return FID < 2 ? DIM : DIM * DIM; }
+template <int DIM, int FID> constexpr int ncomp() { return FID < 2 ? DIM : FID == 4 ? 1 : DIM * DIM; }
+template <int FID> constexpr int slot_of() { return FID == 4 ? 3 : FID; }
 template <int DIM, int FID> constexpr int canon0() {
     return FID == 0 ? 0 : FID == 1 ? DIM : FID == 2 ? 2 * DIM : 2 * DIM + DIM * DIM;
 }
+// material: 0 elastic (slot 3 holds F), 1 fluid (slot 3 holds J)
+template <int MAT> constexpr int fid3() { return MAT ? 4 : 3; }
+template <int DIM, int MAT> constexpr int nc3() { return MAT ? 1 : DIM * DIM; }
 
 // ---------------------------------------------------------------------------
 // Bit pack (Sec. 7, Figs. 7-8), word-major: word k of slot p is
@@ -206,7 +212,7 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const double x = (double)val[c];
-        if (!(x == x)) ls.nan += 1u << (8 * FID);
+        if (!(x == x)) ls.nan += 1u << (8 * slot_of<FID>());
         else M = fmax(M, fabs(x));
     }
     int E;
@@ -238,10 +244,10 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
         uint32_t qc;
         if (q > qmax) {
             qc = f->mag_mask;
-            ls.sat += 1u << (8 * FID);
+            ls.sat += 1u << (8 * slot_of<FID>());
         } else {
             qc = (uint32_t)q;
-            if (RS) ls.ud[FID] += (q > floor(t)) ? 1u : 0x10000u;
+            if (RS) ls.ud[slot_of<FID>()] += (q > floor(t)) ? 1u : 0x10000u;
         }
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
         os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);
@@ -265,7 +271,7 @@ __device__ __forceinline__ void enc_field(const FieldRef f, const T *val, Draws 
             const bool diag = f->rel && (c % (DIM + 1) == 0);
             const double rel = diag ? (double)val[c] - 1.0 : (double)val[c];
             const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
-            const uint32_t code = enc_fixed<RS>(f, rel, r, FID, ls);
+            const uint32_t code = enc_fixed<RS>(f, rel, r, slot_of<FID>(), ls);
             os.emit(code, f->bits);
             const double q = fma((double)code, f->delta, f->lo);
             qv[c] = (T)(diag ? q + 1.0 : q);
@@ -317,22 +323,22 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
 
 
 
-// Decodes the whole record.
-template <int DIM, typename T>
+// Decodes the whole record (F3: F for a solid, J for a fluid).
+template <int DIM, typename T, int MAT>
 __device__ __forceinline__ void decode_all(const DevScheme *sp, const uint32_t *words, int64_t cap, uint32_t p4,
-                                           double *xv, T *vv, T *Cv, T *Fv) {
+                                           double *xv, T *vv, T *Cv, T *F3) {
     SchemeRef s = scheme_ref(sp);
     dec_field<DIM, 0, double>(&s->f[0], words, cap, p4, xv);
     dec_field<DIM, 1, T>(&s->f[1], words, cap, p4, vv);
     dec_field<DIM, 2, T>(&s->f[2], words, cap, p4, Cv);
-    dec_field<DIM, 3, T>(&s->f[3], words, cap, p4, Fv);
+    dec_field<DIM, fid3<MAT>(), T>(&s->f[3], words, cap, p4, F3);
 }
 
 // Encodes all four fields in placement order; qx.. receive the stored values.
-template <int DIM, bool RS>
+template <int DIM, bool RS, int MAT>
 __device__ __forceinline__ void encode_record(const DevScheme *sp, const double *x, const float *v,
-                                              const float *C, const float *F, Draws &rnd, OutStream &os,
-                                              LaneStats &ls, double *qx, float *qv, float *qC, float *qF) {
+                                              const float *C, const float *F3, Draws &rnd, OutStream &os,
+                                              LaneStats &ls, double *qx, float *qv, float *qC, float *qF3) {
     // with a run-time scheme the four fields are one loop (the field order is
     // data); with a compile-time scheme it unrolls and every word boundary of
     // the stream is known at compile time
@@ -347,7 +353,7 @@ __device__ __forceinline__ void encode_record(const DevScheme *sp, const double 
         if (fid == 0) enc_field<DIM, 0, double, RS>(&s->f[0], x, rnd, os, ls, qx);
         else if (fid == 1) enc_field<DIM, 1, float, RS>(&s->f[1], v, rnd, os, ls, qv);
         else if (fid == 2) enc_field<DIM, 2, float, RS>(&s->f[2], C, rnd, os, ls, qC);
-        else enc_field<DIM, 3, float, RS>(&s->f[3], F, rnd, os, ls, qF);
+        else enc_field<DIM, fid3<MAT>(), float, RS>(&s->f[3], F3, rnd, os, ls, qF3);
     }
     os.finish();
 }

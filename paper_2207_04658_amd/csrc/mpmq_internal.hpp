@@ -44,8 +44,9 @@ struct DevScheme {
     int32_t dim, W;
     uint32_t seed_lo, seed_hi;
     uint32_t dither_groups;              // bit j: Philox group j (canonical comps 8j..8j+7) is needed
-    int32_t order[4];                    // placement order of the field ids
-    int32_t pad[3];
+    int32_t order[4];                    // placement order of the state slots (F and J: slot 3)
+    int32_t mat;                         // 0 elastic (slot 3 = F), 1 fluid (slot 3 = J)
+    int32_t pad[2];
     DevField f[4];
 };
 
@@ -63,7 +64,7 @@ constexpr unsigned long long FIX_MAGIC_BITS = 0x4338000000000000ull;
 
 struct DevParams {
     int32_t dim, res, bound, nb;         // nb: node blocks per axis
-    float dt, inv_dx, dx, mu, la, p_mass, stress_over_m, pad;
+    float dt, inv_dx, dx, mu, la, p_mass, stress_over_m, pc;  // pc: fluid pressure coefficient
     float g[3], pad2;
     double dt_d, inv_dx_d;
 };
@@ -95,10 +96,10 @@ struct WorkItem { int32_t block, p0, p1, pad; };
 #ifndef __HIPCC_RTC__
 // ---- launchers (kernels.hip) ----
 
-hipError_t launch_encode(int dim, int wm, const DevScheme *s, const float *x, const float *v,
+hipError_t launch_encode(int dim, int mat, const DevScheme *s, const float *x, const float *v,
                          const float *C, const float *F, int64_t n, int64_t cap, uint32_t *words,
                          uint32_t *ids, uint32_t step, uint32_t tag, uint64_t *stats, hipStream_t st);
-hipError_t launch_decode(int dim, int wm, const DevScheme *s, const uint32_t *words, int64_t n,
+hipError_t launch_decode(int dim, int mat, const DevScheme *s, const uint32_t *words, int64_t n,
                          int64_t cap, float *x, float *v, float *C, float *F, hipStream_t st);
 hipError_t launch_sort_keys(int dim, int wm, const DevScheme *s, const DevParams &p,
                             const uint32_t *words, int64_t n, int64_t cap, uint32_t *keys,
@@ -126,7 +127,7 @@ struct JitKernels {
 // kernels for the current device.  Returns false with a message on failure.
 bool jit_kernels(int dim, const DevScheme &ds, JitKernels *out, std::string *err);
 
-hipError_t launch_p2g(int dim, int wm, const DevScheme *s, const DevParams &p, const uint32_t *words,
+hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, const uint32_t *words,
                       int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
                       GNode *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st,
                       const JitKernels *jit = nullptr);
@@ -134,22 +135,22 @@ hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *g
                               uint32_t *flags_cur, uint32_t *flags_nxt, int64_t nblocks,
                               uint64_t *stats, hipStream_t st);
 hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblocks, hipStream_t st);
-hipError_t launch_substep(int dim, int wm, const DevScheme *s, const DevParams &p, uint32_t *words,
+hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams &p, uint32_t *words,
                           int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
                           const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, uint32_t step,
                           int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st,
                           const JitKernels *jit = nullptr);
 
 // Adjoint (adjoint.hip).  lam buffers: float32 rows x[d], v[d], C[d*d],
-// F[d*d] of n each; nadj: one float4 per grid node; acc: binary64 z, G[4],
+// then F[d*d] (elastic) or J (fluid) of n each; nadj: one float4 per grid node; acc: binary64 z, G[4],
 // g[4]; rng: uint32 order keys min[4], max[4].
-hipError_t launch_adj_objective(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
+hipError_t launch_adj_objective(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
                                 int64_t n, int objective, int axis, float *lam, double *acc, hipStream_t st);
-hipError_t launch_adj_step(int dim, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
+hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
                            int64_t n, const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
                            hipStream_t st);
-hipError_t launch_adj_reduce(int dim, const float *lam, int64_t n, double *acc, hipStream_t st);
-hipError_t launch_adj_range(int dim, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n, uint32_t *rng,
+hipError_t launch_adj_reduce(int dim, int mat, const float *lam, int64_t n, double *acc, hipStream_t st);
+hipError_t launch_adj_range(int dim, int mat, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n, uint32_t *rng,
                             hipStream_t st);
 hipError_t launch_adj_unpermute(const float *lam, const uint32_t *ids, int64_t n, int rows, float *out,
                                 hipStream_t st);

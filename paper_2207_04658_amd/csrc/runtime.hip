@@ -29,30 +29,39 @@ int ceil_log2_double(double hi) {
     return (m == 0.5) ? ex - 1 : ex;
 }
 
-int ncomp(int field, int dim) { return (field == MPMQ_FIELD_X || field == MPMQ_FIELD_V) ? dim : dim * dim; }
+int ncomp(int field, int dim) {
+    return (field == MPMQ_FIELD_X || field == MPMQ_FIELD_V) ? dim : field == MPMQ_FIELD_J ? 1 : dim * dim;
+}
+// state slot of a field: F and J share slot 3
+int slot_of(int field) { return field == MPMQ_FIELD_J ? 3 : field; }
 
 bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::string &err) {
     if (!sc || !sc->fields) { err = "scheme or scheme->fields is NULL"; return false; }
     if (sc->dim != 2 && sc->dim != 3) { err = "scheme dim must be 2 or 3"; return false; }
-    if (sc->n_fields != 4) { err = "scheme must list the 4 fields x, v, C, F"; return false; }
+    if (sc->n_fields != 4) { err = "scheme must list 4 fields: x, v, C and one of F / J"; return false; }
     std::memset(&ds, 0, sizeof(ds));
     ds.dim = sc->dim;
     ds.seed_lo = (uint32_t)sc->seed;
     ds.seed_hi = (uint32_t)(sc->seed >> 32);
     bool seen[4] = {false, false, false, false};
     int off = 0;
-    static const char *names[4] = {"x", "v", "C", "F"};
+    static const char *names[5] = {"x", "v", "C", "F", "J"};
     const int dim = sc->dim;
     for (int i = 0; i < 4; ++i) {
         const mpmq_field_scheme &f = sc->fields[i];
-        if (f.field < 0 || f.field > 3 || seen[f.field]) { err = "fields must be x, v, C, F each exactly once"; return false; }
-        seen[f.field] = true;
-        ds.order[i] = f.field;
+        if (f.field < 0 || f.field > 4 || seen[slot_of(f.field)]) {
+            err = "fields must be x, v, C and one of F / J, each exactly once";
+            return false;
+        }
+        const int sl = slot_of(f.field);
+        seen[sl] = true;
+        ds.order[i] = sl;
+        if (f.field == MPMQ_FIELD_J) ds.mat = 1;
         const char *nm = names[f.field];
         const int nc = ncomp(f.field, dim);
         const bool rel = (f.flags & MPMQ_REL_IDENTITY) != 0;
-        if (rel && f.field != MPMQ_FIELD_F) { err = std::string("REL_IDENTITY is only valid for F (field ") + nm + ")"; return false; }
-        DevField &d = ds.f[f.field];
+        if (rel && sl != 3) { err = std::string("REL_IDENTITY is only valid for F or J (field ") + nm + ")"; return false; }
+        DevField &d = ds.f[sl];
         d.kind = f.kind;
         d.bits = f.bits;
         d.exp_bits = f.exp_bits;
@@ -83,8 +92,8 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
             return false;
         }
         off += nc * f.bits;
-        // canonical component numbering x, v, C, F selects the Philox groups
-        const int k0 = f.field == 0 ? 0 : f.field == 1 ? dim : f.field == 2 ? 2 * dim : 2 * dim + dim * dim;
+        // canonical component numbering x, v, C, then F or J selects the Philox groups
+        const int k0 = sl == 0 ? 0 : sl == 1 ? dim : sl == 2 ? 2 * dim : 2 * dim + dim * dim;
         if (d.dither && f.kind != MPMQ_RAW_F32)
             for (int c = 0; c < nc; ++c) ds.dither_groups |= 1u << ((k0 + c) / 8);
     }
@@ -97,6 +106,7 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
 bool compile_params(const mpmq_params *pp, int dim, DevParams &dp, std::string &err) {
     if (!pp) { err = "params is NULL"; return false; }
     if (pp->dim != dim) { err = "params dim differs from scheme dim"; return false; }
+    if (pp->material != MPMQ_ELASTIC && pp->material != MPMQ_FLUID) { err = "unknown material"; return false; }
     if (pp->grid_res < 8 || pp->grid_res > 1024) { err = "grid_res must be in [8, 1024]"; return false; }
     if (pp->bound_cells < 0 || pp->sort_every < 0) { err = "bound_cells and sort_every must be >= 0"; return false; }
     if (!(pp->dt > 0) || !(pp->E > 0) || !(pp->rho > 0) || !(pp->p_vol > 0) || !(pp->nu > -1.0 && pp->nu < 0.5)) {
@@ -119,6 +129,8 @@ bool compile_params(const mpmq_params *pp, int dim, DevParams &dp, std::string &
     dp.la = (float)la;
     dp.p_mass = (float)(pp->rho * pp->p_vol);
     dp.stress_over_m = (float)(-pp->dt * 4.0 * inv_dx * inv_dx / pp->rho);
+    dp.pc = (float)pp->E;
+    if (pp->material == MPMQ_FLUID) dp.mu = dp.la = 0.0f;
     for (int a = 0; a < 3; ++a) dp.g[a] = (float)pp->gravity[a];
     dp.dt_d = pp->dt;
     dp.inv_dx_d = inv_dx;
@@ -301,7 +313,7 @@ mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
     }
     if (!c->p2g_ready) {
         Timed t(c, "p2g");
-        HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+        HIPCHK(c, launch_p2g(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                              c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st, c->jit_ptr()), "p2g");
     }
     {
@@ -312,7 +324,7 @@ mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
     const bool next_sorts = allow_sort && S > 0 && ((s + 1) % S) == 0;
     {
         Timed t(c, "substep");
-        HIPCHK(c, launch_substep(c->dim, c->wm, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
+        HIPCHK(c, launch_substep(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                                  c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
                                  next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st, c->jit_ptr()),
                "substep");
@@ -332,7 +344,7 @@ mpmq_status reset_grids(mpmq_ctx *c) {
     return MPMQ_OK;
 }
 
-int adj_rows(int dim) { return 2 * dim + 2 * dim * dim; }
+int adj_rows(int dim, int mat) { return 2 * dim + dim * dim + (mat ? 1 : dim * dim); }
 
 // Checkpoint plan of the adjoint: which states the forward pass stores and
 // how many state buffers the backward pass holds at once.
@@ -383,7 +395,7 @@ AdjWork adj_layout(const mpmq_ctx *c, const AdjPlan &plan) {
     const int CPB = c->dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
     w.nodes = c->sp.nblocks * CPB;
     w.state_bytes = 4 * (int64_t)c->W * c->cap_pad;
-    w.lam_bytes = align256(4 * (int64_t)adj_rows(c->dim) * std::max<int64_t>(c->n, 1));
+    w.lam_bytes = align256(4 * (int64_t)adj_rows(c->dim, c->ds.mat) * std::max<int64_t>(c->n, 1));
     int64_t o = 0;
     w.off_states = o; o += plan.slots * w.state_bytes;
     w.off_final = o; o += w.state_bytes;
@@ -460,16 +472,16 @@ struct AdjRun {
         mpmq_status r = reset_grids(c);
         if (r != MPMQ_OK) return r;
         hipStream_t st = c->stream;
-        HIPCHK(c, launch_p2g(c->dim, c->wm, c->dscheme(), c->dp, words, c->cap_pad, c->items(), c->n_items(),
+        HIPCHK(c, launch_p2g(c->dim, c->ds.mat, c->dscheme(), c->dp, words, c->cap_pad, c->items(), c->n_items(),
                              c->launch_grid, c->grid[0], c->flags(0), c->stats(), st, c->jit_ptr()), "adjoint: p2g");
         HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[0], c->grid[1], c->flags(0), c->flags(1), c->sp.nblocks,
                                      c->stats(), st), "adjoint: grid update");
         {
             Timed tm(c, "adjoint_step");
-            HIPCHK(c, launch_adj_step(c->dim, c->dscheme(), c->dp, words, c->cap_pad, c->n, c->grid[0], w.nodes,
+            HIPCHK(c, launch_adj_step(c->dim, c->ds.mat, c->dscheme(), c->dp, words, c->cap_pad, c->n, c->grid[0], w.nodes,
                                       lam_cur, lam_nxt, nadj(), st), "adjoint: step");
         }
-        HIPCHK(c, launch_adj_reduce(c->dim, lam_nxt, c->n, acc(), st), "adjoint: reduce");
+        HIPCHK(c, launch_adj_reduce(c->dim, c->ds.mat, lam_nxt, c->n, acc(), st), "adjoint: reduce");
         std::swap(lam_cur, lam_nxt);
         return MPMQ_OK;
     }
@@ -535,6 +547,8 @@ mpmq_status mpmq_query_sizes(const mpmq_scheme *scheme, const mpmq_params *param
     std::string err;
     if (!compile_scheme(scheme, ds, bits, err)) return fail(nullptr, MPMQ_EINVAL, err);
     if (!compile_params(params, ds.dim, dp, err)) return fail(nullptr, MPMQ_EINVAL, err);
+    if ((params->material == MPMQ_FLUID) != (ds.mat == 1))
+        return fail(nullptr, MPMQ_EINVAL, "material must match the scheme: F for ELASTIC, J for FLUID");
     if (capacity < 1 || capacity > (int64_t)0x3fffff00) return fail(nullptr, MPMQ_ENOMEM, "capacity must be in [1, 2^30-256]");
     const int64_t cap_pad = (capacity + 255) & ~(int64_t)255;
     const Scratch sp = plan_scratch(ds.dim, dp.res, cap_pad);
@@ -611,7 +625,7 @@ mpmq_status mpmq_encode(mpmq_ctx *c, const float *x, const float *v, const float
     if (n > 0 && (!x || !v || !C || !F)) return fail(c, MPMQ_EINVAL, "x, v, C and F are required");
     {
         Timed t(c, "encode");
-        HIPCHK(c, launch_encode(c->dim, c->wm, c->dscheme(), x, v, C, F, n, c->cap_pad, c->words, c->ids,
+        HIPCHK(c, launch_encode(c->dim, c->ds.mat, c->dscheme(), x, v, C, F, n, c->cap_pad, c->words, c->ids,
                                 (uint32_t)c->step, 2u, c->stats(), c->stream), "encode");
     }
     c->n = n;
@@ -624,7 +638,7 @@ mpmq_status mpmq_decode(mpmq_ctx *c, float *x, float *v, float *C, float *F) {
     if (!c) return fail(nullptr, MPMQ_EINVAL, "ctx is NULL");
     if (!c->encoded) return fail(c, MPMQ_ESTATE, "decode before encode");
     Timed t(c, "decode");
-    HIPCHK(c, launch_decode(c->dim, c->wm, c->dscheme(), c->words, c->n, c->cap_pad, x, v, C, F, c->stream), "decode");
+    HIPCHK(c, launch_decode(c->dim, c->ds.mat, c->dscheme(), c->words, c->n, c->cap_pad, x, v, C, F, c->stream), "decode");
     return MPMQ_OK;
 }
 
@@ -764,7 +778,7 @@ mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
     std::memset(out, 0, sizeof(*out));
     hipStream_t st = c->stream;
     const int64_t n = c->n;
-    const int rows = adj_rows(c->dim);
+    const int rows = adj_rows(c->dim, c->ds.mat);
     if (n == 0) {
         c->step += T;
         c->steps_taken += T;
@@ -791,7 +805,7 @@ mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
     }
     size_t save_i = 0;
     for (int64_t t = 0; t <= T; ++t) {
-        HIPCHK(c, launch_adj_range(c->dim, c->dscheme(), c->words, c->cap_pad, n, run.rng(), st), "adjoint: ranges");
+        HIPCHK(c, launch_adj_range(c->dim, c->ds.mat, c->dscheme(), c->words, c->cap_pad, n, run.rng(), st), "adjoint: ranges");
         if (save_i < plan.forward_saves.size() && plan.forward_saves[save_i] == t) {
             const int s = run.take();
             if ((r = run.copy_state(c->words, run.slot_ptr(s))) != MPMQ_OK) return r;
@@ -805,9 +819,9 @@ mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
                               2 * ST_COUNT, st), "adjoint: stats");
     if ((r = run.copy_state(c->words, run.final_ptr())) != MPMQ_OK) return r;
     // objective at s_T and lambda_T
-    HIPCHK(c, launch_adj_objective(c->dim, c->dscheme(), c->dp, c->words, c->cap_pad, n, spec->objective, spec->axis,
+    HIPCHK(c, launch_adj_objective(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, n, spec->objective, spec->axis,
                                    run.lam_cur, run.acc(), st), "adjoint: objective");
-    HIPCHK(c, launch_adj_reduce(c->dim, run.lam_cur, n, run.acc(), st), "adjoint: reduce");
+    HIPCHK(c, launch_adj_reduce(c->dim, c->ds.mat, run.lam_cur, n, run.acc(), st), "adjoint: reduce");
     // backward
     if (T > 0) {
         if (spec->checkpoint_every >= 1) {

@@ -84,7 +84,7 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
 // order of magnitude slower on this part, and integer sums are
 // order-independent).
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int MAT>
 __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
                                              const float *C, const float *F, const int *origin,
                                              unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
@@ -103,29 +103,36 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
         w[a][1] = wf[1];
         w[a][2] = wf[2];
     }
-    // fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + lambda J (J-1) I
-    float R[D2];
-    float J;
-    if constexpr (DIM == 2) {
-        polar2(F, R);
-        J = F[0] * F[3] - F[1] * F[2];
-    } else {
-        polar3(F, R);
-        J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
-            F[2] * (F[3] * F[7] - F[4] * F[6]);
-    }
     // A / m_p = -4 dt / (rho dx^2) tau + C
     float Am[D2];
+    if constexpr (MAT == 1) {
+        // fluid: tau = pc (J - 1) I, J = F[0]
+        const float t = P.stress_over_m * P.pc * (F[0] - 1.0f);
 #pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-            float t = 0.0f;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
-            t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
-            Am[i * DIM + j] = P.stress_over_m * t + C[i * DIM + j];
+        for (int i = 0; i < D2; ++i) Am[i] = C[i] + ((i % (DIM + 1) == 0) ? t : 0.0f);
+    } else {
+        // fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + lambda J (J-1) I
+        float R[D2];
+        float J;
+        if constexpr (DIM == 2) {
+            polar2(F, R);
+            J = F[0] * F[3] - F[1] * F[2];
+        } else {
+            polar3(F, R);
+            J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                F[2] * (F[3] * F[7] - F[4] * F[6]);
         }
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                float t = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) t += (F[i * DIM + k] - R[i * DIM + k]) * F[j * DIM + k];
+                t = 2.0f * P.mu * t + ((i == j) ? P.la * J * (J - 1.0f) : 0.0f);
+                Am[i * DIM + j] = P.stress_over_m * t + C[i * DIM + j];
+            }
+    }
     // node value = w (q + sum_b a_b o_b), q = v - (A/m) f dx, a_b = (A/m)[:, b] dx, scaled by 2^32
     double q[DIM], ac[DIM][DIM];  // ac[b][a]
 #pragma unroll
@@ -274,7 +281,7 @@ struct ItemWalk {
 // ---------------------------------------------------------------------------
 // bootstrap P2G from the packed state (after a sort or an encode)
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_p2g(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
                                             int64_t cap, const WorkItem *__restrict__ items,
                                             const uint32_t *__restrict__ n_items, GNode *__restrict__ gout,
@@ -293,9 +300,9 @@ __global__ __launch_bounds__(WG) void k_p2g(const DevScheme *__restrict__ sch, D
         __syncthreads();
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
             double xd[DIM];
-            float v[DIM], C[D2], F[D2];
-            decode_all<DIM, float>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
-            p2g_particle<DIM>(P, xd, v, C, F, origin, acc, gout, flags, fallback);
+            float v[DIM], C[D2], F[nc3<DIM, MAT>()];
+            decode_all<DIM, float, MAT>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
+            p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback);
         }
         __syncthreads();
         tile_flush<DIM>(P, origin, acc, gout, flags);
@@ -402,7 +409,7 @@ __device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int n
     }
 }
 
-template <int DIM, bool RS>
+template <int DIM, bool RS, int MAT>
 __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__ sch, DevParams P, uint32_t *words,
                                                 int64_t cap, const WorkItem *__restrict__ items,
                                                 const uint32_t *__restrict__ n_items,
@@ -437,10 +444,11 @@ __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
             SchemeRef sp = scheme_ref(sch);
             const uint32_t p4 = (uint32_t)p * 4u;
+            constexpr int N3 = nc3<DIM, MAT>();
             double xd[DIM];
-            float F[D2];
+            float F[N3];
             dec_field<DIM, 0, double>(&sp->f[0], words, cap, p4, xd);
-            dec_field<DIM, 3, float>(&sp->f[3], words, cap, p4, F);
+            dec_field<DIM, fid3<MAT>(), float>(&sp->f[3], words, cap, p4, F);
             int base[DIM];
             float fx[DIM], wx[DIM][3], wd[DIM][3];
             stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
@@ -469,8 +477,9 @@ __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__
                 g2p_global<DIM>(gcur, P.nb, base, wx, wd, nv, S);
             }
             // update: x' = x + dt v' (binary64), C' = 4/dx S, F' = (I + dt C') F
+            // (fluid: J' = J (1 + dt tr C'))
             double xn[DIM];
-            float Cn[D2], Fn[D2];
+            float Cn[D2], Fn[N3];
             {
 #pragma clang fp contract(off)
 #pragma unroll
@@ -480,24 +489,31 @@ __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__
             for (int a = 0; a < DIM; ++a)
 #pragma unroll
                 for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] = 4.0f * P.inv_dx * S[b][a];
+            if constexpr (MAT == 1) {
+                float tr = 0.0f;
 #pragma unroll
-            for (int i = 0; i < DIM; ++i)
+                for (int a = 0; a < DIM; ++a) tr += Cn[a * DIM + a];
+                Fn[0] = F[0] * (1.0f + P.dt * tr);
+            } else {
 #pragma unroll
-                for (int j = 0; j < DIM; ++j) {
-                    float t = F[i * DIM + j];
+                for (int i = 0; i < DIM; ++i)
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) t += P.dt * Cn[i * DIM + k] * F[k * DIM + j];
-                    Fn[i * DIM + j] = t;
-                }
+                    for (int j = 0; j < DIM; ++j) {
+                        float t = F[i * DIM + j];
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k) t += P.dt * Cn[i * DIM + k] * F[k * DIM + j];
+                        Fn[i * DIM + j] = t;
+                    }
+            }
             // dithered encode (Eq. 11), streamed in place in placement order
             Draws rnd;
             rnd.init(seed_ref(sch), (uint32_t)p, step, 1u);
             OutStream os{words, cap, p4, 0ull, 0, 0};
             double qx[DIM];
-            float qv[DIM], qC[D2], qF[D2];
-            encode_record<DIM, RS>(sch, xn, nv, Cn, Fn, rnd, os, ls, qx, qv, qC, qF);
+            float qv[DIM], qC[D2], qF[N3];
+            encode_record<DIM, RS, MAT>(sch, xn, nv, Cn, Fn, rnd, os, ls, qx, qv, qC, qF);
             // P2G of the stored (quantized) state for the next substep (Eq. 1)
-            if (do_p2g) p2g_particle<DIM>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
+            if (do_p2g) p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
         }
         __syncthreads();
         if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags);

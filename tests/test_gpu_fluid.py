@@ -1,0 +1,120 @@
+"""Fluid material (state x, v, C, J) on the GPU against the FP64 oracle:
+codec bit-exact on identical inputs, dam-break trajectories, the specialized
+kernels, and the adjoint (average height = centre of mass along y, and
+kinetic energy)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from gpu_common import by_id, gpu_context, gpu_decode_np, note, oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+
+def fluid_state(rng, dim, n):
+    x, v, C, _ = WL.random_state(rng, dim, n)
+    J = (1.0 + 0.3 * rng.uniform(-1, 1, (1, n))).astype(np.float32)
+    k = min(n, 6)
+    J[0, :k] = np.array([1.0, 0.5, 1.5, 2.0, np.nan, 1.0 + 2.0 ** -17], dtype=np.float32)[:k]
+    return x, v, C, J
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dither", [False, True])
+@pytest.mark.parametrize("n", [1, 777])
+def test_fluid_codec_bit_exact(gpu_lib, orc, dim, dither, n):
+    note(f"fluid codec dim={dim} dither={dither} n={n}")
+    scheme = WL.scheme_fluid(dim, dither, seed=3)
+    state = fluid_state(np.random.default_rng(n + dim), dim, n)
+    scene = {"scheme": scheme, "params": WL.params(dim, 64, 1e-4, 1e-6, material="fluid", E=WL.FLUID_E),
+             "state": state}
+    ctx = gpu_context(gpu_lib, scene)
+    ow, ost = orc.encode(scheme, *state, 0, 2)
+    assert np.array_equal(ctx.words(), ow)
+    gst = ctx.stats()
+    for f in ("x", "v", "C", "J"):
+        assert gst[f] == ost[f], f
+    dec = gpu_decode_np(ctx)
+    odec = orc.decode(scheme, ow)
+    assert dec[3].shape == (1, n)
+    for a, b in zip(dec, odec):
+        assert np.array_equal(a.astype(np.float32), b.astype(np.float32))
+    ctx.close()
+
+
+def test_fluid_scheme_material_mismatch(gpu_lib):
+    sc = WL.dam_break(2, grid_res=32, ppc=2)
+    bad = dict(sc["params"], material="elastic")
+    with pytest.raises(gpu_lib.MpmqError):
+        gpu_lib.Context(sc["scheme"], bad, sc["n"])
+
+
+@pytest.mark.parametrize("dim,res,ppc,steps", [(2, 64, 4, 30), (3, 32, 2, 12)])
+@pytest.mark.parametrize("dither", [False, True])
+def test_dam_break_vs_oracle(gpu_lib, orc, dim, res, ppc, steps, dither):
+    note(f"dam break dim={dim} res={res} dither={dither} steps={steps}")
+    sc = WL.dam_break(dim, seed=1, grid_res=res, ppc=ppc, steps=steps, dither=dither, sort_every=7)
+    ctx = gpu_context(gpu_lib, sc)
+    ctx.step(steps)
+    sim, _, _ = oracle_sim(orc, sc)
+    sim.step(steps)
+    g = gpu_decode_np(ctx)
+    o = orc.decode(sc["scheme"], sim.words())
+    gi, oi = ctx.ids(), sim.ids()
+    xg, xo = by_id(g[0], gi), by_id(o[0], oi)
+    assert np.max(np.abs(xg - xo)) <= 1e-4
+    Jg, Jo = by_id(g[3], gi), by_id(o[3], oi)
+    assert np.max(np.abs(Jg - Jo)) <= 4 * 2.0 ** -16 + 1e-6
+    sim.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fluid_specialized_equals_generic(gpu_lib, dim):
+    note(f"fluid specialized vs generic dim={dim}")
+    sc = WL.dam_break(dim, seed=2, grid_res=32, ppc=2, dither=True, sort_every=5)
+    gen = gpu_context(gpu_lib, sc)
+    spe = gpu_context(gpu_lib, sc)
+    spe.specialize(True)
+    for k in (4, 7):
+        gen.step(k)
+        spe.step(k)
+        assert np.array_equal(gen.words(), spe.words())
+    gen.close()
+    spe.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("kind", ["com", "ke"])
+def test_fluid_adjoint_vs_oracle(gpu_lib, orc, dim, kind):
+    note(f"fluid adjoint dim={dim} objective={kind}")
+    sc = WL.dam_break(dim, seed=4, grid_res=32 if dim == 2 else 16, ppc=2, dither=True, sort_every=0)
+    T = 6
+    ctx = gpu_context(gpu_lib, sc)
+    res = ctx.adjoint(T, objective=kind, axis=1, checkpoint_every=2, want_lambda0=True)
+    lg = res["lambda0"].cpu().numpy().astype(np.float64)
+    x, v, C, J = sc["state"]
+    w0, _ = orc.encode(sc["scheme"], x, v, C, J, 0, 2)
+    sim = orc.Sim(sc["scheme"], sc["params"], w0)
+    states = [orc.pack_state(*orc.decode(sc["scheme"], w0))]
+    for _ in range(T):
+        sim.step(1)
+        states.append(by_id(orc.pack_state(*orc.decode(sc["scheme"], sim.words())), sim.ids()))
+    sim.close()
+    z, G, g, A, lo = orc.adjoint_full(sc["params"], states, kind, 1)
+    assert math.isclose(res["z"], z, rel_tol=1e-5 if kind == "com" else 3e-3), (res["z"], z)
+    rows = orc.field_rows(dim, "fluid")
+    steps = {"x": 2.0 ** -20, "v": 40.0 * 2.0 ** -16, "C": 2048.0 * 2.0 ** -15, "J": 2.0 ** -16}
+    top = max(float(np.max(np.abs(lo[a:b]))) * steps[f] for f, (a, b) in rows.items())
+    for f, (a, b) in rows.items():
+        err = float(np.max(np.abs(lg[a:b] - lo[a:b]))) * steps[f]
+        own = float(np.max(np.abs(lo[a:b]))) * steps[f]
+        assert err <= 2e-2 * top, (f, err, top)
+        if own >= 1e-3 * top:
+            assert err <= 2e-2 * own, (f, err, own)
+        gw, gow = res["g"][f] * steps[f] ** 2, g[f] * steps[f] ** 2
+        gtop = max(g[h] * steps[h] ** 2 for h in rows)
+        assert abs(gw - gow) <= 3e-2 * max(gow, 1e-3 * gtop), (f, res["g"][f], g[f])
+    ctx.close()
