@@ -39,6 +39,9 @@ static int grid_for(int64_t n, int per_block = 256) {
 // ---------------------------------------------------------------------------
 // encode / decode (float32 SoA <-> packed words)
 // ---------------------------------------------------------------------------
+// Grid-stride over particles; statistics are summed per lane in 32-bit
+// counters and flushed once per work-group (per-wave flushes of a few shared
+// counters would serialize in the L2).
 template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_encode(const DevScheme *__restrict__ sch, const float *__restrict__ x,
                                                const float *__restrict__ v, const float *__restrict__ C,
@@ -46,10 +49,12 @@ __global__ __launch_bounds__(WG) void k_encode(const DevScheme *__restrict__ sch
                                                uint32_t *words, uint32_t *__restrict__ ids,
                                                uint32_t step, uint32_t tag, uint64_t *stats) {
     constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
-    LaneStats ls;
-    ls.clear();
-    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (p < n) {
+    uint32_t cnt[16];  // up[4], down[4], sat[4], nan[4]
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cnt[i] = 0u;
+    for (int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x; p < n; p += (int64_t)gridDim.x * WG) {
+        LaneStats ls;
+        ls.clear();
         double xv[DIM], qx[DIM];
         float vv[DIM], Cv[D2], Fv[N3], qv[DIM], qC[D2], qF[N3];
 #pragma unroll
@@ -66,8 +71,29 @@ __global__ __launch_bounds__(WG) void k_encode(const DevScheme *__restrict__ sch
         OutStream os{words, cap, (uint32_t)p * 4u, 0ull, 0, 0};
         encode_record<DIM, true, MAT>(sch, xv, vv, Cv, Fv, rnd, os, ls, qx, qv, qC, qF);
         if (ids) ids[p] = (uint32_t)p;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            cnt[f] += ls.ud[f] & 0xffffu;
+            cnt[4 + f] += ls.ud[f] >> 16;
+            cnt[8 + f] += (ls.sat >> (8 * f)) & 0xffu;
+            cnt[12 + f] += (ls.nan >> (8 * f)) & 0xffu;
+        }
     }
-    flush_stats(ls, stats);
+    __shared__ uint32_t part[WG / 64][16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t w = wave_sum(cnt[i]);
+        if (__lane_id() == 0) part[threadIdx.x >> 6][i] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < WG / 64; ++k) tot += part[k][threadIdx.x];
+        const int f = threadIdx.x & 3, kind = threadIdx.x >> 2;
+        const int slot = kind == 0 ? ST_UP : kind == 1 ? ST_DOWN : kind == 2 ? ST_SAT : ST_NAN;
+        if (tot) atomicAdd((unsigned long long *)&stats[slot + f], (unsigned long long)tot);
+    }
 }
 
 
@@ -397,7 +423,19 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restri
         }
     }
     if (tn && threadIdx.x == 0) fnxt[b] = 0u;
-    add_stat(stats, ST_ACTIVE, active);
+    // one atomic per work-group, spread over ST_ACTIVE_SLOTS counters: a
+    // single counter hit by every wave serializes in the L2
+    __shared__ uint32_t wsum[WG / 64];
+    const uint32_t ws = wave_sum(active);
+    if (__lane_id() == 0) wsum[threadIdx.x >> 6] = ws;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int i = 0; i < WG / 64; ++i) tot += wsum[i];
+        if (tot)
+            atomicAdd((unsigned long long *)&stats[ST_ACTIVE + (b % ST_ACTIVE_SLOTS)], (unsigned long long)tot);
+    }
 }
 
 template <int DIM>
@@ -448,7 +486,8 @@ hipError_t launch_encode(int dim, int mat, const DevScheme *s, const float *x, c
                          const float *F, int64_t n, int64_t cap, uint32_t *words, uint32_t *ids, uint32_t step,
                          uint32_t tag, uint64_t *stats, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    MPMQ_DISPATCH_M(dim, mat, k_encode, pgrid(n), s, x, v, C, F, n, cap, words, ids, step, tag, stats);
+    const dim3 g((unsigned)std::min<int64_t>((n + WG - 1) / WG, 4096));
+    MPMQ_DISPATCH_M(dim, mat, k_encode, g, s, x, v, C, F, n, cap, words, ids, step, tag, stats);
     return hipGetLastError();
 }
 

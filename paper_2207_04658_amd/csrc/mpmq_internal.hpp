@@ -71,7 +71,7 @@ struct DevParams {
 
 // Statistics slots (uint64) in scratch.
 enum {
-    ST_SAT = 0, ST_NAN = 4, ST_UP = 8, ST_DOWN = 12, ST_FALLBACK = 16, ST_ACTIVE = 17,
+    ST_SAT = 0, ST_NAN = 4, ST_UP = 8, ST_DOWN = 12, ST_FALLBACK = 16, ST_ACTIVE = 17, ST_ACTIVE_SLOTS = 7,
     ST_COUNT = 24
 };
 

@@ -687,7 +687,8 @@ mpmq_status mpmq_stats(mpmq_ctx *c, mpmq_stats_t *out) {
     out->steps = c->steps_taken;
     out->sorts = c->sorts;
     out->fallback = (int64_t)h[ST_FALLBACK];
-    out->active_nodes = (int64_t)h[ST_ACTIVE];
+    out->active_nodes = 0;
+    for (int i = 0; i < ST_ACTIVE_SLOTS; ++i) out->active_nodes += (int64_t)h[ST_ACTIVE + i];
     return MPMQ_OK;
 }
 

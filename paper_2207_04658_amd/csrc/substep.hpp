@@ -19,6 +19,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 __device__ __forceinline__ void flush_stats(const LaneStats &ls, uint64_t *stats) {
+    if (!__any((ls.ud[0] | ls.ud[1] | ls.ud[2] | ls.ud[3] | ls.sat | ls.nan) != 0u)) return;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         const uint32_t up = wave_sum(ls.ud[f] & 0xffffu);
