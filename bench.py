@@ -46,6 +46,23 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: one VALU lane-instruction per cycle
+
+
+def read_valu(config):
+    """VALU wave-instructions per substep launch from the committed counter
+    summary (same source hash as the traffic), or None."""
+    path = os.path.join(ROOT, "profiles", f"substep_{config}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", txt)
+    m = re.search(r"valu_wave_instructions_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not m_hash or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m.group(1))
+
+
 def read_traffic(config):
     """HBM bytes per substep launch from the committed rocprofv3 counter
     summary, if it was taken with the current kernel sources."""
@@ -91,6 +108,28 @@ def build_scene(config, device):
                 "F 9x14b fixed (F-I), dithered")
         scene = {"name": "c3", "scheme": scheme, "params": params, "n": n, "desc": desc, "grid": 512,
                  "steps_cfg": 10}
+    elif config == "fluid":
+        # 3D fluid dam break: a column [0.1,0.4]x[0.1,0.6]x[0.3,0.7] of a 512^3 grid, 8 particles
+        # per cell (64.4M particles), generated on the device from a seeded torch generator
+        res, ppc = 512, 8
+        lo = torch.tensor([0.1, 0.1, 0.3], dtype=torch.float64)
+        hi = torch.tensor([0.4, 0.6, 0.7], dtype=torch.float64)
+        n = int(round(float(torch.prod((hi - lo) * res)) * ppc))
+        gen = torch.Generator(device=device)
+        gen.manual_seed(7)
+        x = torch.rand((3, n), generator=gen, device=device, dtype=torch.float32)
+        x = (lo.to(device).float()[:, None] + (hi - lo).to(device).float()[:, None] * x).contiguous()
+        v = torch.zeros((3, n), dtype=torch.float32, device=device)
+        J = torch.ones((1, n), dtype=torch.float32, device=device)
+        C = torch.zeros((9, n), dtype=torch.float32, device=device)
+        vol = float(torch.prod(hi - lo))
+        params = WL.params(3, res, 5e-5, vol / n, sort_every=0, material="fluid", E=WL.FLUID_E)
+        desc = (f"3D MLS-MPM fluid dam break, {n} particles (8 per cell) in [0.1,0.4]x[0.1,0.6]x[0.3,0.7] of a "
+                "512^3 grid, dt=5e-5, pressure coefficient 400; x 3x20b fixed, v 3x16b fixed, C 9x16b shared-exp "
+                "(6b), J 16b fixed (J-1), dithered")
+        scene = {"name": "fluid", "scheme": WL.scheme_fluid(3, True, 0), "params": params, "n": n, "desc": desc,
+                 "grid": res, "steps_cfg": 10, "fp32_scheme": WL.scheme_fluid_fp32(3)}
+        return scene, (x, v, C, J)
     else:
         sc = WL.c2() if config == "c2" else WL.c1()
         xh, vh, _, _ = sc["state"]
@@ -182,6 +221,16 @@ def cpu_baseline(scene):
     elif scene["name"] == "c2":
         sub = WL.c2(cubes=1)
         sample = f"cube 0 of 4 ({sub['n']} particles) on the 128^3 grid, 3 substeps after a warm-up substep"
+    elif scene["name"] == "fluid":
+        # a slab x in [0.1, 0.1075) of the column at the same density (8 per cell) on the 512^3 grid
+        rng = np.random.default_rng(3)
+        lo, hi = np.array([0.1, 0.1, 0.3]), np.array([0.1075, 0.6, 0.7])
+        ns = int(round(float(np.prod((hi - lo) * 512)) * 8))
+        xs = (lo[:, None] + (hi - lo)[:, None] * rng.random((3, ns))).astype(np.float32)
+        state = (xs, np.zeros((3, ns), np.float32), np.zeros((9, ns), np.float32), np.ones((1, ns), np.float32))
+        sub = {"scheme": scene["scheme"], "params": scene["params"], "n": ns, "state": state}
+        sample = (f"a slab of {ns} particles of the dam-break column (same density) on the full 512^3 grid, "
+                  f"3 substeps after a warm-up substep")
     else:
         sub = WL.c1()
         sample = "the full scene (8192 particles), 3 substeps after a warm-up substep"
@@ -296,7 +345,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fluid"])
     ap.add_argument("--scenes", type=int, default=256, help="c4: scenes in the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="c4: Poisson arrival rate (scenes/s)")
     ap.add_argument("--no-fp32", action="store_true")
@@ -331,16 +380,25 @@ def main():
         out["quant"] = run_layout(mq, scene, scene["scheme"], state, a.steps, a.warmup, "quantized",
                                   specialize=not a.generic)
     if a.only == "fp32" or (a.only is None and not a.no_fp32):
-        out["fp32"] = run_layout(mq, scene, WL.scheme_fp32(scene["params"]["dim"]), state, a.steps, a.warmup,
-                                 "fp32 layout", specialize=not a.generic)
+        fp32_scheme = scene.get("fp32_scheme") or WL.scheme_fp32(scene["params"]["dim"])
+        out["fp32"] = run_layout(mq, scene, fp32_scheme, state, a.steps, a.warmup, "fp32 layout",
+                                 specialize=not a.generic)
     del state
     torch.cuda.empty_cache()
     main_res = out.get("quant") or out["fp32"]
     rf = roofline(main_res, n, a.steps)
-    traffic, tstate = read_traffic(scene["name"])
+    traffic, tstate = read_traffic(scene["name"]) if not a.generic else (None, "counters are of the specialized kernel")
     if rf is not None:
         rf["traffic"] = traffic
         rf["traffic_status"] = tstate or "no counter summary"
+        valu = read_valu(scene["name"]) if not a.generic else None
+        if valu is not None:
+            # the fused kernel is limited by vector-ALU issue: its counted VALU
+            # lane-instructions per second against one per lane per cycle
+            ach = valu * 64 / (rf["avg_launch_ms"] / 1e3)
+            rf["valu_issue"] = {"achieved": round(ach / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                                "unit": "T lane-instr/s", "frac": round(ach / VALU_PEAK_LANE_OPS, 4),
+                                "instructions_per_launch": valu}
     cpu = None
     if not a.no_cpu:
         log("cpu baseline (oracle) ...")
