@@ -436,8 +436,9 @@ def main():
         line["speedup_vs_fp32"] = round(q["value"] / f["value"], 4)
         line["compression_vs_fp32"] = round(f["bytes_per_particle"] / q["bytes_per_particle"], 4)
         line["fp32_roofline"] = roofline(f, n, a.steps)
-    line["saturations"] = {k: main_res["stats"][k]["sat"] for k in "xvCF"}
-    line["nan"] = {k: main_res["stats"][k]["nan"] for k in "xvCF"}
+    fields = [k for k in ("x", "v", "C", "F", "J") if k in main_res["stats"]]
+    line["saturations"] = {k: main_res["stats"][k]["sat"] for k in fields}
+    line["nan"] = {k: main_res["stats"][k]["nan"] for k in fields}
     line["fallback_stencils"] = main_res["stats"]["fallback"]
     print(json.dumps(line), flush=True)
 

@@ -462,22 +462,23 @@ __global__ __launch_bounds__(WG) void k_clear_touched(GNode *__restrict__ g, uin
         else hipLaunchKernelGGL((KERNEL<2>), GRID, dim3(WG), 0, st, __VA_ARGS__);                 \
     } while (0)
 
-// dimension x material
-#define MPMQ_DISPATCH_M(dim, mat, KERNEL, GRID, ...)                                                    \
+// dimension x material, work-group of NT threads
+#define MPMQ_DISPATCH_MB(dim, mat, KERNEL, GRID, NT, ...)                                               \
     do {                                                                                               \
-        if ((dim) == 3 && (mat)) hipLaunchKernelGGL((KERNEL<3, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);  \
-        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);      \
-        else if (mat) hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);             \
-        else hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);                      \
+        if ((dim) == 3 && (mat)) hipLaunchKernelGGL((KERNEL<3, 1>), GRID, dim3(NT), 0, st, __VA_ARGS__);  \
+        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, 0>), GRID, dim3(NT), 0, st, __VA_ARGS__);      \
+        else if (mat) hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(NT), 0, st, __VA_ARGS__);             \
+        else hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(NT), 0, st, __VA_ARGS__);                      \
     } while (0)
+#define MPMQ_DISPATCH_M(dim, mat, KERNEL, GRID, ...) MPMQ_DISPATCH_MB(dim, mat, KERNEL, GRID, WG, __VA_ARGS__)
 
-// dimension x flag x material
+// dimension x flag x material (particle-tile kernels)
 #define MPMQ_DISPATCH2(dim, mat, KERNEL, FLAG, GRID, ...)                                                    \
     do {                                                                                                    \
-        if ((dim) == 3 && (mat)) hipLaunchKernelGGL((KERNEL<3, FLAG, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__); \
-        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, FLAG, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);     \
-        else if (mat) hipLaunchKernelGGL((KERNEL<2, FLAG, 1>), GRID, dim3(WG), 0, st, __VA_ARGS__);            \
-        else hipLaunchKernelGGL((KERNEL<2, FLAG, 0>), GRID, dim3(WG), 0, st, __VA_ARGS__);                     \
+        if ((dim) == 3 && (mat)) hipLaunchKernelGGL((KERNEL<3, FLAG, 1>), GRID, dim3(PWG), 0, st, __VA_ARGS__); \
+        else if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3, FLAG, 0>), GRID, dim3(PWG), 0, st, __VA_ARGS__);     \
+        else if (mat) hipLaunchKernelGGL((KERNEL<2, FLAG, 1>), GRID, dim3(PWG), 0, st, __VA_ARGS__);            \
+        else hipLaunchKernelGGL((KERNEL<2, FLAG, 0>), GRID, dim3(PWG), 0, st, __VA_ARGS__);                     \
     } while (0)
 
 static dim3 pgrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
@@ -576,9 +577,9 @@ hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, 
         DevParams pv = p;
         void *args[] = {(void *)&s, &pv, (void *)&words, &cap, (void *)&items, (void *)&n_items, &gout, &flags_out,
                         &stats};
-        return hipModuleLaunchKernel(jit->p2g, (unsigned)grid, 1, 1, WG, 1, 1, 0, st, args, nullptr);
+        return hipModuleLaunchKernel(jit->p2g, (unsigned)grid, 1, 1, PWG, 1, 1, 0, st, args, nullptr);
     }
-    MPMQ_DISPATCH_M(dim, mat, k_p2g, dim3(grid), s, p, words, cap, items, n_items, gout, flags_out, stats);
+    MPMQ_DISPATCH_MB(dim, mat, k_p2g, dim3(grid), PWG, s, p, words, cap, items, n_items, gout, flags_out, stats);
     return hipGetLastError();
 }
 
@@ -609,7 +610,7 @@ hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams 
         DevParams pv = p;
         void *args[] = {(void *)&s, &pv, &words, &cap, (void *)&items, (void *)&n_items, (void *)&gcur, &gnxt,
                         &flags_nxt, &step, &do_p2g, &collect_stats, &stats};
-        return hipModuleLaunchKernel(jit->substep[round_stats ? 1 : 0], (unsigned)grid, 1, 1, WG, 1, 1, 0, st, args,
+        return hipModuleLaunchKernel(jit->substep[round_stats ? 1 : 0], (unsigned)grid, 1, 1, PWG, 1, 1, 0, st, args,
                                      nullptr);
     }
     if (round_stats)

@@ -182,20 +182,12 @@ __device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, doub
     const double t = (val - f->lo) * f->inv;
     const double sv = t + r;
     const double fl = floor(sv);
-    uint32_t code;
-    if (!(sv == sv)) {
-        code = 0u;
-        ls.nan += 1u << (8 * fid);
-    } else if (fl < 0.0) {
-        code = 0u;
-        ls.sat += 1u << (8 * fid);
-    } else if (fl > f->maxc) {
-        code = (uint32_t)f->maxc;
-        ls.sat += 1u << (8 * fid);
-    } else {
-        code = (uint32_t)fl;
-        if (RS) ls.ud[fid] += (fl > floor(t)) ? 1u : 0x10000u;
-    }
+    // selects rather than branches: the counters are per-lane registers
+    const bool nan = !(sv == sv), below = fl < 0.0, above = fl > f->maxc;
+    const uint32_t code = (nan || below) ? 0u : above ? (uint32_t)f->maxc : (uint32_t)fl;
+    ls.nan += nan ? 1u << (8 * fid) : 0u;
+    ls.sat += (below || above) ? 1u << (8 * fid) : 0u;
+    if (RS) ls.ud[fid] += (nan || below || above) ? 0u : (fl > floor(t)) ? 1u : 0x10000u;
     return code;
 }
 
@@ -212,43 +204,40 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const double x = (double)val[c];
-        if (!(x == x)) ls.nan += 1u << (8 * slot_of<FID>());
-        else M = fmax(M, fabs(x));
+        ls.nan += (x == x) ? 0u : 1u << (8 * slot_of<FID>());
+        M = fmax(M, fabs(x));  // fmax ignores a NaN operand
     }
     int E;
     if (M == 0.0) E = f->emin;
     else if (isinf(M)) E = f->emax;
     else E = min(max(ilogb(M) + 1, f->emin), f->emax);
     // raise E while a magnitude rounds up to 2^(m-1) (at most once in exact
-    // arithmetic; the loop keeps the definition literal)
+    // arithmetic; the loop keeps the definition literal); the rounded
+    // magnitudes of the last pass are the codes
+    double tq[NC], qq[NC];
     for (;;) {
-        bool over = false;
+        double qtop = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             double x = (double)val[c];
             x = (x == x) ? fabs(x) : 0.0;
             const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
-            over |= floor(ldexp(x, m1 - E) + r) > qmax;
+            tq[c] = ldexp(x, m1 - E);
+            qq[c] = floor(tq[c] + r);
+            qtop = fmax(qtop, qq[c]);
         }
-        if (!(over && E < f->emax)) break;
+        if (!(qtop > qmax && E < f->emax)) break;
         E += 1;
     }
     os.emit((uint32_t)(E - f->emin), f->exp_bits);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double x = (double)val[c];
-        x = (x == x) ? fabs(x) : 0.0;
-        const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
-        const double t = ldexp(x, m1 - E);
-        const double q = floor(t + r);
-        uint32_t qc;
-        if (q > qmax) {
-            qc = f->mag_mask;
-            ls.sat += 1u << (8 * slot_of<FID>());
-        } else {
-            qc = (uint32_t)q;
-            if (RS) ls.ud[slot_of<FID>()] += (q > floor(t)) ? 1u : 0x10000u;
-        }
+        const double t = tq[c];
+        const double q = qq[c];
+        const bool above = q > qmax;
+        const uint32_t qc = above ? f->mag_mask : (uint32_t)q;
+        ls.sat += above ? 1u << (8 * slot_of<FID>()) : 0u;
+        if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
         os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);
         const double mag = ldexp((double)qc, E - m1);
@@ -408,9 +397,8 @@ __device__ __forceinline__ void bspline(float f, float *w) {
 
 // Rotation of the polar decomposition F = R S.
 // 2D: closed form from the rotation angle of F.
-// 3D: Newton iteration R <- (R + R^-T)/2 from R = F, until all lanes of the
-// wave have converged (at most 16 iterations); quadratic convergence near
-// the identity.
+// 3D: Newton iteration R <- (R + R^-T)/2 from R = F, until every lane of the
+// wave has taken a step shorter than 3e-5 (at most 16 iterations).
 __device__ __forceinline__ void polar2(const float *F, float *R) {
     float c = F[0] + F[3], s = F[2] - F[1];
     const float r2 = c * c + s * s;
@@ -450,7 +438,10 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
             d2 += d * d;
             R[i] = ok ? Rn[i] : ((i % 4 == 0) ? 1.0f : 0.0f);
         }
-        if (!__any(d2 > 1e-13f)) break;
+        // Newton's polar iteration converges quadratically: the error of the
+        // new iterate is about |R_new - R|^2 / (2 sigma_min), below 1e-9 once
+        // the step is under 3e-5, far below float precision
+        if (!__any(d2 > 1e-9f)) break;
     }
 }
 

@@ -30,6 +30,13 @@ template <> struct Geo<2> {
 };
 
 constexpr int WG = 256;          // threads per work-group of the particle kernels
+// Threads per work-group of the particle-tile kernels (bootstrap P2G and the
+// fused substep).  In 3D a group stages 76 KB of node tile in LDS, so two
+// groups share a CU's 160 KB: two waves per SIMD, up to 256 VGPRs per lane.
+// (384-thread groups, three waves per SIMD, measured 25 % slower on the
+// 3e8-particle workload.)
+constexpr int PWG = 256;
+constexpr int PWG_WAVES_PER_EU = 2;
 constexpr int MAX_WORDS = 32;    // record <= 1024 bits
 
 // One field's codec constants (indexed by field id x=0, v=1, C=2, F=3).

@@ -252,8 +252,9 @@ mpmq_status do_sort(mpmq_ctx *c) {
     const int cpb = c->dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
     uint32_t *cells = c->u32(s.cells);
     // item size: enough items to fill the chip on small scenes, big tiles on large ones
-    int cap = 256;
-    while (cap < 4096 && (int64_t)cap * 2 * 2048 <= n) cap *= 2;
+    // (a multiple of the particle work-group, at most 16 passes of it)
+    int cap = PWG;
+    while (cap < 16 * PWG && (int64_t)cap * 2 * 2048 <= n) cap *= 2;
     c->item_cap = cap;
     const int64_t upper = std::min<int64_t>(s.nblocks, n) + (n + cap - 1) / cap + 1;
     // persistent grid, a multiple of the 8 XCDs (see ItemWalk)

@@ -59,12 +59,11 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
     for (int s = 0; s < NST; ++s) {
         const int o[3] = {s % 3, (s / 3) % 3, s / 9};
         int ijk[DIM];
-        double wt = 1.0;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            ijk[a] = base[a] + o[a];
-            wt *= w[a][o[a]];
-        }
+        for (int a = 0; a < DIM; ++a) ijk[a] = base[a] + o[a];
+        // the same products, in the same order, as the tile path
+        const double wr = (DIM == 3) ? w[2][o[2]] * w[1][o[1]] : w[1][o[1]];
+        const double wt = wr * w[0][o[0]];
         unsigned long long *g = gout[node_index<DIM>(ijk, P.nb)].q;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -73,7 +72,7 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
             for (int b = 0; b < DIM; ++b) val += ac[b][a] * (double)o[b];
             atomicAdd(g + a, fixp(wt, val));
         }
-        atomicAdd(g + 3, fixp(wt, FIX_ONE));
+        atomicAdd(g + 3, fixp(w[0][o[0]], wr * FIX_ONE));
         flags[block_of<DIM>(ijk, P.nb)] = 1u;
     }
 }
@@ -171,6 +170,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
 #pragma unroll
                         for (int a = 0; a < 3; ++a) vzy[a] += ac[1][a];
                     const double wzy = w[2][oz] * w[1][oy];
+                    const double m32 = wzy * FIX_ONE;  // exact (power-of-two scale)
                     double val[3] = {vzy[0], vzy[1], vzy[2]};
 #pragma unroll
                     for (int ox = 0; ox < 3; ++ox) {
@@ -181,7 +181,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                         const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
-                        atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
+                        atomicAdd(&acc[3 * TN + idx], fixp(w[0][ox], m32));
                     }
                 }
             }
@@ -192,6 +192,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                 if (oy > 0)
 #pragma unroll
                     for (int a = 0; a < 2; ++a) vy[a] += ac[1][a];
+                const double m32 = w[1][oy] * FIX_ONE;  // exact (power-of-two scale)
                 double val[2] = {vy[0], vy[1]};
 #pragma unroll
                 for (int ox = 0; ox < 3; ++ox) {
@@ -202,7 +203,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                     const int idx = l0 + oy * TB + ox;
 #pragma unroll
                     for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
-                    atomicAdd(&acc[3 * TN + idx], fixp(wt, FIX_ONE));
+                    atomicAdd(&acc[3 * TN + idx], fixp(w[0][ox], m32));
                 }
             }
         }
@@ -246,7 +247,7 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
                                            const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
                                            uint32_t *__restrict__ flags) {
     constexpr int TN = Geo<DIM>::TN;
-    for (int t = threadIdx.x; t < TN; t += WG) {
+    for (int t = threadIdx.x; t < TN; t += PWG) {
         const unsigned long long a0 = acc[t], a1 = acc[TN + t], a2 = acc[2 * TN + t], m = acc[3 * TN + t];
         if ((a0 | a1 | a2 | m) != 0ull) {
             int ijk[DIM];
@@ -283,7 +284,7 @@ struct ItemWalk {
 // bootstrap P2G from the packed state (after a sort or an encode)
 // ---------------------------------------------------------------------------
 template <int DIM, int MAT>
-__global__ __launch_bounds__(WG) void k_p2g(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
+__global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *__restrict__ sch, DevParams P, const uint32_t *__restrict__ words,
                                             int64_t cap, const WorkItem *__restrict__ items,
                                             const uint32_t *__restrict__ n_items, GNode *__restrict__ gout,
                                             uint32_t *__restrict__ flags, uint64_t *stats) {
@@ -297,9 +298,9 @@ __global__ __launch_bounds__(WG) void k_p2g(const DevScheme *__restrict__ sch, D
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
-        for (int t = threadIdx.x; t < 4 * TN; t += WG) acc[t] = 0ull;
+        for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
         __syncthreads();
-        for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
+        for (int p = it.p0 + threadIdx.x; p < it.p1; p += PWG) {
             double xd[DIM];
             float v[DIM], C[D2], F[nc3<DIM, MAT>()];
             decode_all<DIM, float, MAT>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
@@ -411,7 +412,7 @@ __device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int n
 }
 
 template <int DIM, bool RS, int MAT>
-__global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__ sch, DevParams P, uint32_t *words,
+__global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevScheme *__restrict__ sch, DevParams P, uint32_t *words,
                                                 int64_t cap, const WorkItem *__restrict__ items,
                                                 const uint32_t *__restrict__ n_items,
                                                 const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
-        for (int t = threadIdx.x; t < TN; t += WG) {
+        for (int t = threadIdx.x; t < TN; t += PWG) {
             int ijk[DIM];
             float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (tile_node<DIM>(t, origin, P.res, ijk))
@@ -440,9 +441,9 @@ __global__ __launch_bounds__(WG, 2) void k_substep(const DevScheme *__restrict__
             if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
         }
         if (do_p2g)
-            for (int t = threadIdx.x; t < 4 * TN; t += WG) acc[t] = 0ull;
+            for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
         __syncthreads();
-        for (int p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
+        for (int p = it.p0 + threadIdx.x; p < it.p1; p += PWG) {
             SchemeRef sp = scheme_ref(sch);
             const uint32_t p4 = (uint32_t)p * 4u;
             constexpr int N3 = nc3<DIM, MAT>();
