@@ -1,10 +1,12 @@
 // jit.hip -- host side of scheme specialization: compiles the fused substep
-// and bootstrap P2G kernels (substep.hpp) with hipRTC, the scheme of a
-// context written into the source as a compile-time DevScheme, so that field
-// kinds, bit offsets, masks and codec constants fold into the instruction
-// stream.  The arithmetic is the same source under the same device flags,
-// so results equal the generic kernels'.  Code objects are cached per
-// process by (device, dimension, scheme).
+// and bootstrap P2G kernels (substep.hpp) with hipRTC, the scheme and the
+// simulation parameters of a context written into the source as
+// compile-time DevScheme / DevParams values, so that field kinds, bit
+// offsets, masks, codec constants and parameters fold into the instruction
+// stream (and need no scalar registers).  The arithmetic is the same source
+// under the same device flags, so results equal the generic kernels'.
+// Code objects are cached per process by (device, dimension, scheme,
+// parameters).
 #include "mpmq_internal.hpp"
 
 #include <hip/hiprtc.h>
@@ -51,12 +53,22 @@ std::string initializer(const DevScheme &d) {
     return s;
 }
 
-bool compile(int dim, int mat, const std::string &init, std::vector<char> &code, std::string lowered[3],
-             std::string *err) {
+// C++ initializer of a DevParams (floats as exact hexadecimal literals).
+std::string initializer(const DevParams &p) {
+    auto hf = [](float v) { return hexd((double)v) + "f"; };
+    return "{" + std::to_string(p.dim) + ", " + std::to_string(p.res) + ", " + std::to_string(p.bound) + ", " +
+           std::to_string(p.nb) + ", " + hf(p.dt) + ", " + hf(p.inv_dx) + ", " + hf(p.dx) + ", " + hf(p.mu) + ", " +
+           hf(p.la) + ", " + hf(p.p_mass) + ", " + hf(p.stress_over_m) + ", " + hf(p.pc) + ", {" + hf(p.g[0]) + ", " +
+           hf(p.g[1]) + ", " + hf(p.g[2]) + "}, 0.0f, " + hexd(p.dt_d) + ", " + hexd(p.inv_dx_d) + "}";
+}
+
+bool compile(int dim, int mat, const std::string &init, const std::string &pinit, std::vector<char> &code,
+             std::string lowered[3], std::string *err) {
     const std::string d = std::to_string(dim), m = std::to_string(mat);
     const std::string names[3] = {"mpmq::k_substep<" + d + ", false, " + m + ">",
                                   "mpmq::k_substep<" + d + ", true, " + m + ">", "mpmq::k_p2g<" + d + ", " + m + ">"};
-    const std::string src = "#define MPMQ_SCHEME_CONST " + init + "\n#include \"substep.hpp\"\n";
+    const std::string src = "#define MPMQ_SCHEME_CONST " + init + "\n#define MPMQ_PARAMS_CONST " + pinit +
+                            "\n#include \"substep.hpp\"\n";
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "mpmq_specialized.hip", kJitHeaderCount, kJitHeaders,
                             kJitHeaderNames) != HIPRTC_SUCCESS) {
@@ -93,14 +105,14 @@ bool compile(int dim, int mat, const std::string &init, std::vector<char> &code,
 
 }  // namespace
 
-bool jit_kernels(int dim, const DevScheme &ds, JitKernels *out, std::string *err) {
+bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, JitKernels *out, std::string *err) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         *err = "hipGetDevice failed";
         return false;
     }
-    const std::string init = initializer(ds);
-    const std::string key = std::to_string(dev) + "/" + std::to_string(dim) + "/" + init;
+    const std::string init = initializer(ds), pinit = initializer(dp);
+    const std::string key = std::to_string(dev) + "/" + std::to_string(dim) + "/" + init + "/" + pinit;
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
@@ -109,7 +121,7 @@ bool jit_kernels(int dim, const DevScheme &ds, JitKernels *out, std::string *err
     }
     std::vector<char> code;
     std::string lowered[3];
-    if (!compile(dim, ds.mat, init, code, lowered, err)) return false;
+    if (!compile(dim, ds.mat, init, pinit, code, lowered, err)) return false;
     Entry e;
     hipError_t h = hipModuleLoadData(&e.mod, code.data());
     for (int i = 0; h == hipSuccess && i < 3; ++i) {

@@ -29,6 +29,14 @@ template <typename P> __device__ __forceinline__ P opaque(P v) {
 typedef const __attribute__((address_space(4))) DevScheme *SchemeRef;
 typedef const __attribute__((address_space(4))) DevField *FieldRef;
 __device__ __forceinline__ SchemeRef seed_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
+// The same holds for the simulation parameters (MPMQ_PARAMS_CONST, a
+// DevParams initializer): a context's parameters never change.
+#ifdef MPMQ_PARAMS_CONST
+static constexpr DevParams kParamsConst = MPMQ_PARAMS_CONST;
+__device__ __forceinline__ const DevParams &params_ref(const DevParams &) { return kParamsConst; }
+#else
+__device__ __forceinline__ const DevParams &params_ref(const DevParams &p) { return p; }
+#endif
 #ifdef MPMQ_SCHEME_CONST
 static constexpr DevScheme kSchemeConst = MPMQ_SCHEME_CONST;
 __device__ __forceinline__ SchemeRef scheme_ref(const DevScheme *) { return (SchemeRef)&kSchemeConst; }
