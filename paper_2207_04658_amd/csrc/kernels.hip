@@ -376,53 +376,68 @@ __global__ __launch_bounds__(WG) void k_items(const uint32_t *__restrict__ cell_
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double from_fix(unsigned long long v) { return (double)(long long)v; }
 
+// Persistent: work-group g walks node blocks g, g + gridDim.x, ...; a block
+// flagged in fcur gets its fixed-point sums turned into float4 (v, m) in
+// place, a block flagged in fnxt is cleared for the next P2G.  One count
+// atomic per work-group.
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restrict__ gcur,
                                                     GNode *__restrict__ gnxt, uint32_t *__restrict__ fcur,
                                                     uint32_t *__restrict__ fnxt, int64_t nblocks, uint64_t *stats) {
     constexpr int B = Geo<DIM>::BLK, CPB = Geo<DIM>::CPB, L = Geo<DIM>::LOG;
-    const int64_t b = blockIdx.x;
-    const bool tc = fcur[b] != 0u, tn = fnxt[b] != 0u;
-    if (!tc && !tn) return;
-    int bc[3] = {0, 0, 0};
-    bc[0] = (int)(b % P.nb);
-    if constexpr (DIM == 3) {
-        bc[1] = (int)((b / P.nb) % P.nb);
-        bc[2] = (int)(b / ((int64_t)P.nb * P.nb));
-    } else {
-        bc[1] = (int)(b / P.nb);
-    }
+    static_assert(CPB % WG == 0, "a node block is a whole number of work-group passes");
     uint32_t active = 0;
-    for (int l = threadIdx.x; l < CPB; l += WG) {
-        const int64_t idx = (b << (DIM * L)) + l;
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const bool tc = fcur[b] != 0u, tn = fnxt[b] != 0u;
+        // every wave has read fnxt[b] before thread 0 resets it below (the
+        // waves of a group do not run in lockstep)
+        __syncthreads();
+        if (!tc && !tn) continue;
+        int bc[3] = {0, 0, 0};
+        bc[0] = (int)(b % P.nb);
+        if constexpr (DIM == 3) {
+            bc[1] = (int)((b / P.nb) % P.nb);
+            bc[2] = (int)(b / ((int64_t)P.nb * P.nb));
+        } else {
+            bc[1] = (int)(b / P.nb);
+        }
         if (tc) {
-            const GNode g = gcur[idx];
-            const double m = from_fix(g.q[3]);
-            float vel[3] = {0.0f, 0.0f, 0.0f};
-            if (m > 0.0) {
-                ++active;
-                int ijk[3];
-                ijk[0] = bc[0] * B + (l & (B - 1));
-                ijk[1] = bc[1] * B + ((l >> L) & (B - 1));
-                ijk[2] = (DIM == 3) ? bc[2] * B + (l >> (2 * L)) : 0;
+            // all loads of the block first (CPB / WG nodes per thread)
+            GNode g[CPB / WG];
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    float va = (float)(from_fix(g.q[a]) / m) + P.dt * P.g[a];
-                    if (ijk[a] < P.bound && va < 0.0f) va = 0.0f;
-                    if (ijk[a] >= P.res - P.bound && va > 0.0f) va = 0.0f;
-                    vel[a] = va;
+            for (int r = 0; r < CPB / WG; ++r) g[r] = gcur[(b << (DIM * L)) + threadIdx.x + r * WG];
+#pragma unroll
+            for (int r = 0; r < CPB / WG; ++r) {
+                const int l = threadIdx.x + r * WG;
+                const double m = from_fix(g[r].q[3]);
+                float vel[3] = {0.0f, 0.0f, 0.0f};
+                if (m > 0.0) {
+                    ++active;
+                    int ijk[3];
+                    ijk[0] = bc[0] * B + (l & (B - 1));
+                    ijk[1] = bc[1] * B + ((l >> L) & (B - 1));
+                    ijk[2] = (DIM == 3) ? bc[2] * B + (l >> (2 * L)) : 0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        float va = (float)(from_fix(g[r].q[a]) / m) + P.dt * P.g[a];
+                        if (ijk[a] < P.bound && va < 0.0f) va = 0.0f;
+                        if (ijk[a] >= P.res - P.bound && va > 0.0f) va = 0.0f;
+                        vel[a] = va;
+                    }
                 }
+                const float mass = m > 0.0 ? (float)(m * (1.0 / FIX_ONE)) * P.p_mass : 0.0f;
+                reinterpret_cast<float4 *>(gcur + (b << (DIM * L)) + l)[0] = make_float4(vel[0], vel[1], vel[2], mass);
             }
-            const float mass = m > 0.0 ? (float)(m * (1.0 / FIX_ONE)) * P.p_mass : 0.0f;
-            reinterpret_cast<float4 *>(gcur + idx)[0] = make_float4(vel[0], vel[1], vel[2], mass);
         }
         if (tn) {
             ulonglong4 z;
             z.x = z.y = z.z = z.w = 0ull;
-            reinterpret_cast<ulonglong4 *>(gnxt + idx)[0] = z;
+#pragma unroll
+            for (int r = 0; r < CPB / WG; ++r)
+                reinterpret_cast<ulonglong4 *>(gnxt + (b << (DIM * L)) + threadIdx.x + r * WG)[0] = z;
+            if (threadIdx.x == 0) fnxt[b] = 0u;
         }
     }
-    if (tn && threadIdx.x == 0) fnxt[b] = 0u;
     // one atomic per work-group, spread over ST_ACTIVE_SLOTS counters: a
     // single counter hit by every wave serializes in the L2
     __shared__ uint32_t wsum[WG / 64];
@@ -434,7 +449,8 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restri
 #pragma unroll
         for (int i = 0; i < WG / 64; ++i) tot += wsum[i];
         if (tot)
-            atomicAdd((unsigned long long *)&stats[ST_ACTIVE + (b % ST_ACTIVE_SLOTS)], (unsigned long long)tot);
+            atomicAdd((unsigned long long *)&stats[ST_ACTIVE + (blockIdx.x % ST_ACTIVE_SLOTS)],
+                      (unsigned long long)tot);
     }
 }
 
@@ -443,7 +459,9 @@ __global__ __launch_bounds__(WG) void k_clear_touched(GNode *__restrict__ g, uin
                                                       int64_t nblocks) {
     constexpr int CPB = Geo<DIM>::CPB, L = Geo<DIM>::LOG;
     const int64_t b = blockIdx.x;
-    if (flags[b] == 0u) return;
+    const bool touched = flags[b] != 0u;
+    __syncthreads();  // every wave has read the flag before thread 0 resets it
+    if (!touched) return;
     for (int l = threadIdx.x; l < CPB; l += WG) {
         ulonglong4 z;
         z.x = z.y = z.z = z.w = 0ull;
@@ -585,12 +603,13 @@ hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, 
 
 hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *gnxt, uint32_t *flags_cur,
                               uint32_t *flags_nxt, int64_t nblocks, uint64_t *stats, hipStream_t st) {
+    const dim3 grid((unsigned)std::min<int64_t>(nblocks, 4096));
     if (dim == 3)
-        hipLaunchKernelGGL(k_grid_update<3>, dim3((unsigned)nblocks), dim3(WG), 0, st, p, gcur, gnxt, flags_cur,
-                           flags_nxt, nblocks, stats);
+        hipLaunchKernelGGL(k_grid_update<3>, grid, dim3(WG), 0, st, p, gcur, gnxt, flags_cur, flags_nxt, nblocks,
+                           stats);
     else
-        hipLaunchKernelGGL(k_grid_update<2>, dim3((unsigned)nblocks), dim3(WG), 0, st, p, gcur, gnxt, flags_cur,
-                           flags_nxt, nblocks, stats);
+        hipLaunchKernelGGL(k_grid_update<2>, grid, dim3(WG), 0, st, p, gcur, gnxt, flags_cur, flags_nxt, nblocks,
+                           stats);
     return hipGetLastError();
 }
 
