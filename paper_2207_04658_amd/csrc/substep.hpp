@@ -263,7 +263,8 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
 }
 
 // ---------------------------------------------------------------------------
-// Persistent work-item walk.  Work-groups are dispatched round-robin over the
+// Work-item walk (a group takes one item or several, depending on the grid
+// size).  Work-groups are dispatched round-robin over the
 // 8 XCDs (each with its own L2), so work-group b runs on XCD b % 8; XCD x
 // walks the contiguous range [x*chunk, (x+1)*chunk) of the block-ordered
 // items, so spatially adjacent tiles (which share halo nodes) meet in the
