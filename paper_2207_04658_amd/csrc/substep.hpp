@@ -242,11 +242,17 @@ __device__ __forceinline__ bool tile_node(int t, const int *origin, int res, int
     return ok;
 }
 
+// Adds the tile's non-zero node sums to the grid with int64 atomics and flags
+// the node blocks that received data.  A tile (origin = block corner - 1)
+// overlaps 3 node blocks per axis: its first node layer lies in the block
+// before, the next BLK in its own block, the rest in the block after.  The
+// flags go through `touched` (LDS, 3^DIM entries, zero on entry and on
+// return): one global store per touched block instead of one per node.
 template <int DIM>
 __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin,
                                            const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
-                                           uint32_t *__restrict__ flags) {
-    constexpr int TN = Geo<DIM>::TN;
+                                           uint32_t *__restrict__ flags, uint32_t *touched) {
+    constexpr int TN = Geo<DIM>::TN, TB = Geo<DIM>::TB, B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
     for (int t = threadIdx.x; t < TN; t += PWG) {
         const unsigned long long a0 = acc[t], a1 = acc[TN + t], a2 = acc[2 * TN + t], m = acc[3 * TN + t];
         if ((a0 | a1 | a2 | m) != 0ull) {
@@ -257,7 +263,32 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
             atomicAdd(g + 1, a1);
             if (DIM == 3) atomicAdd(g + 2, a2);
             atomicAdd(g + 3, m);
-            flags[block_of<DIM>(ijk, P.nb)] = 1u;
+            int k = 0;
+#pragma unroll
+            for (int a = DIM - 1; a >= 0; --a) {
+                const int l = ijk[a] - origin[a];  // 0 .. TB-1
+                k = 3 * k + ((l == 0) ? 0 : (l <= B) ? 1 : 2);
+            }
+            touched[k] = 1u;
+        }
+    }
+    static_assert(TB - 1 - B <= B, "a tile spans at most three blocks per axis");
+    __syncthreads();
+    constexpr int NB3 = (DIM == 3) ? 27 : 9;
+    if (threadIdx.x < NB3) {
+        if (touched[threadIdx.x]) {
+            int k = threadIdx.x;
+            int64_t blk = 0;
+#pragma unroll
+            for (int a = DIM - 1; a >= 0; --a) {
+                int d = k;
+#pragma unroll
+                for (int e = 0; e < a; ++e) d /= 3;
+                d = d % 3;
+                blk = blk * P.nb + (((origin[a] + 1) >> L) + d - 1);
+            }
+            flags[blk] = 1u;
+            touched[threadIdx.x] = 0u;
         }
     }
 }
@@ -292,6 +323,8 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
     const DevParams &P = params_ref(Parg);
     constexpr int TN = Geo<DIM>::TN, D2 = DIM * DIM;
     __shared__ unsigned long long acc[4 * TN];
+    __shared__ uint32_t touched[27];
+    if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const uint32_t nit = *n_items;
     uint32_t fallback = 0;
     const ItemWalk walk(nit);
@@ -309,7 +342,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
             p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback);
         }
         __syncthreads();
-        tile_flush<DIM>(P, origin, acc, gout, flags);
+        tile_flush<DIM>(P, origin, acc, gout, flags, touched);
     }
     add_stat(stats, ST_FALLBACK, fallback);
 }
@@ -424,6 +457,8 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
     __shared__ float gv[DIM * TN];
     __shared__ unsigned long long acc[4 * TN];
+    __shared__ uint32_t touched[27];
+    if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const uint32_t nit = *n_items;
     uint32_t fallback = 0;
     LaneStats ls;
@@ -521,7 +556,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             if (do_p2g) p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
         }
         __syncthreads();
-        if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags);
+        if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags, touched);
         if (collect_stats) {
             flush_stats(ls, stats);
             ls.clear();
