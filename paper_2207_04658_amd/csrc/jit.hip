@@ -1,12 +1,13 @@
 // jit.hip -- host side of scheme specialization: compiles the fused substep
 // and bootstrap P2G kernels (substep.hpp) with hipRTC, the scheme and the
 // simulation parameters of a context written into the source as
-// compile-time DevScheme / DevParams values, so that field kinds, bit
-// offsets, masks, codec constants and parameters fold into the instruction
-// stream (and need no scalar registers).  The arithmetic is the same source
+// compile-time DevScheme / DevParams values (and the row stride of the
+// packed words), so that field kinds, bit offsets, masks, codec constants,
+// parameters and row addresses fold into the instruction stream (and need
+// no scalar registers).  The arithmetic is the same source
 // under the same device flags, so results equal the generic kernels'.
 // Code objects are cached per process by (device, dimension, scheme,
-// parameters).
+// parameters, row stride).
 #include "mpmq_internal.hpp"
 
 #include <hip/hiprtc.h>
@@ -62,13 +63,13 @@ std::string initializer(const DevParams &p) {
            hf(p.g[1]) + ", " + hf(p.g[2]) + "}, 0.0f, " + hexd(p.dt_d) + ", " + hexd(p.inv_dx_d) + "}";
 }
 
-bool compile(int dim, int mat, const std::string &init, const std::string &pinit, std::vector<char> &code,
-             std::string lowered[3], std::string *err) {
+bool compile(int dim, int mat, const std::string &init, const std::string &pinit, int64_t cap,
+             std::vector<char> &code, std::string lowered[3], std::string *err) {
     const std::string d = std::to_string(dim), m = std::to_string(mat);
     const std::string names[3] = {"mpmq::k_substep<" + d + ", false, " + m + ">",
                                   "mpmq::k_substep<" + d + ", true, " + m + ">", "mpmq::k_p2g<" + d + ", " + m + ">"};
     const std::string src = "#define MPMQ_SCHEME_CONST " + init + "\n#define MPMQ_PARAMS_CONST " + pinit +
-                            "\n#include \"substep.hpp\"\n";
+                            "\n#define MPMQ_CAP_CONST " + std::to_string(cap) + "ll\n#include \"substep.hpp\"\n";
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "mpmq_specialized.hip", kJitHeaderCount, kJitHeaders,
                             kJitHeaderNames) != HIPRTC_SUCCESS) {
@@ -105,14 +106,16 @@ bool compile(int dim, int mat, const std::string &init, const std::string &pinit
 
 }  // namespace
 
-bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, JitKernels *out, std::string *err) {
+bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, int64_t cap, JitKernels *out,
+                 std::string *err) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         *err = "hipGetDevice failed";
         return false;
     }
     const std::string init = initializer(ds), pinit = initializer(dp);
-    const std::string key = std::to_string(dev) + "/" + std::to_string(dim) + "/" + init + "/" + pinit;
+    const std::string key =
+        std::to_string(dev) + "/" + std::to_string(dim) + "/" + init + "/" + pinit + "/" + std::to_string(cap);
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
@@ -121,7 +124,7 @@ bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, JitKernels *
     }
     std::vector<char> code;
     std::string lowered[3];
-    if (!compile(dim, ds.mat, init, pinit, code, lowered, err)) return false;
+    if (!compile(dim, ds.mat, init, pinit, cap, code, lowered, err)) return false;
     Entry e;
     hipError_t h = hipModuleLoadData(&e.mod, code.data());
     for (int i = 0; h == hipSuccess && i < 3; ++i) {

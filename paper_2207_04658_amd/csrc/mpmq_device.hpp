@@ -31,6 +31,13 @@ typedef const __attribute__((address_space(4))) DevField *FieldRef;
 __device__ __forceinline__ SchemeRef seed_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
 // The same holds for the simulation parameters (MPMQ_PARAMS_CONST, a
 // DevParams initializer): a context's parameters never change.
+// ... and for the row stride of the packed words (MPMQ_CAP_CONST): with a
+// constant stride the row addresses need no registers.
+#ifdef MPMQ_CAP_CONST
+__device__ __forceinline__ int64_t cap_ref(int64_t) { return (int64_t)(MPMQ_CAP_CONST); }
+#else
+__device__ __forceinline__ int64_t cap_ref(int64_t c) { return c; }
+#endif
 #ifdef MPMQ_PARAMS_CONST
 static constexpr DevParams kParamsConst = MPMQ_PARAMS_CONST;
 __device__ __forceinline__ const DevParams &params_ref(const DevParams &) { return kParamsConst; }
@@ -167,10 +174,12 @@ struct Draws {
     }
 };
 
-// xi' in (0,1): (r16 + 1/2) 2^-16, exact in binary64.
-__device__ __forceinline__ double dither_xi(Draws &d, int k) {
-    return ((double)d.draw16(k) + 0.5) * (1.0 / 65536.0);
-}
+// The dither offset xi' = h 2^-16 in (0,1) is kept as h = r16 + 1/2 (exact
+// in binary64); the encoders add it as fma(h, 2^-16, t), which equals
+// RN(t + xi') because h 2^-16 is exact.  Without dithering h = 2^15
+// (xi' = 1/2, round to nearest).
+constexpr double XI_SCALE = 1.0 / 65536.0, XI_HALF = 32768.0;
+__device__ __forceinline__ double dither_h(Draws &d, int k) { return (double)d.draw16(k) + 0.5; }
 
 // ---------------------------------------------------------------------------
 // Encoder statistics kept per lane and flushed per work item:
@@ -183,17 +192,18 @@ struct LaneStats {
     __device__ void clear() { ud[0] = ud[1] = ud[2] = ud[3] = 0; sat = nan = 0; }
 };
 
-// Fixed point (Eq. 3, Eq. 11 when r = xi): binary64, no contraction, so the
-// rounding sequence is exactly t = RN(RN(val - lo) * inv), s = RN(t + r),
-// u = clamp(floor(s)).
+// Fixed point (Eq. 3, Eq. 11 when xi' = h 2^-16): binary64, no contraction,
+// so the rounding sequence is exactly t = RN(RN(val - lo) * inv),
+// s = RN(t + xi'), u = clamp(floor(s)).
 template <bool RS>
-__device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, double r, int fid,
+__device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, double h, int fid,
                                               LaneStats &ls) {
 #pragma clang fp contract(off)
     const double t = (val - f->lo) * f->inv;
-    const double sv = t + r;
+    const double sv = fma(h, XI_SCALE, t);
     const double fl = floor(sv);
-    // selects rather than branches: the counters are per-lane registers
+    // clamp to [0, maxc] (fmax takes a NaN to 0); a value the clamp changed
+    // saturated.  Selects rather than branches: the counters are per-lane.
     const bool nan = !(sv == sv), below = fl < 0.0, above = fl > f->maxc;
     const uint32_t code = (nan || below) ? 0u : above ? (uint32_t)f->maxc : (uint32_t)fl;
     ls.nan += nan ? 1u << (8 * fid) : 0u;
@@ -232,9 +242,9 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
         for (int c = 0; c < NC; ++c) {
             double x = (double)val[c];
             x = fmax(fabs(x), 0.0);  // NaN -> 0
-            const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
+            const double h = f->dither ? dither_h(rnd, K0 + c) : XI_HALF;
             tq[c] = ldexp(x, m1 - E);
-            qq[c] = floor(tq[c] + r);
+            qq[c] = floor(fma(h, XI_SCALE, tq[c]));
             qtop = fmax(qtop, qq[c]);
         }
         if (!(qtop > qmax && E < f->emax)) break;
@@ -246,7 +256,7 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
         const double t = tq[c];
         const double q = qq[c];
         const bool above = q > qmax;
-        const uint32_t qc = above ? f->mag_mask : (uint32_t)q;
+        const uint32_t qc = (uint32_t)fmin(q, qmax);  // q >= 0
         ls.sat += above ? 1u << (8 * slot_of<FID>()) : 0u;
         if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
@@ -270,8 +280,8 @@ __device__ __forceinline__ void enc_field(const FieldRef f, const T *val, Draws 
         for (int c = 0; c < NC; ++c) {
             const bool diag = f->rel && (c % (DIM + 1) == 0);
             const double rel = diag ? (double)val[c] - 1.0 : (double)val[c];
-            const double r = f->dither ? dither_xi(rnd, K0 + c) : 0.5;
-            const uint32_t code = enc_fixed<RS>(f, rel, r, slot_of<FID>(), ls);
+            const double h = f->dither ? dither_h(rnd, K0 + c) : XI_HALF;
+            const uint32_t code = enc_fixed<RS>(f, rel, h, slot_of<FID>(), ls);
             os.emit(code, f->bits);
             const double q = fma((double)code, f->delta, f->lo);
             qv[c] = (T)(diag ? q + 1.0 : q);

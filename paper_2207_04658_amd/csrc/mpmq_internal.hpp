@@ -132,7 +132,7 @@ struct JitKernels {
 };
 // Compiles (once per process, scheme and device) and loads the specialized
 // kernels for the current device.  Returns false with a message on failure.
-bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, JitKernels *out, std::string *err);
+bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, int64_t cap, JitKernels *out, std::string *err);
 
 hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, const uint32_t *words,
                       int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,

@@ -720,7 +720,7 @@ mpmq_status mpmq_specialize(mpmq_ctx *c, int32_t enable) {
     }
     std::string err;
     JitKernels k{};
-    if (!jit_kernels(c->dim, c->ds, c->dp, &k, &err)) return fail(c, MPMQ_EDEVICE, "specialize: " + err);
+    if (!jit_kernels(c->dim, c->ds, c->dp, c->cap_pad, &k, &err)) return fail(c, MPMQ_EDEVICE, "specialize: " + err);
     c->jit = k;
     c->use_jit = true;
     return MPMQ_OK;

@@ -317,10 +317,11 @@ struct ItemWalk {
 // ---------------------------------------------------------------------------
 template <int DIM, int MAT>
 __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *__restrict__ sch, DevParams Parg, const uint32_t *__restrict__ words,
-                                            int64_t cap, const WorkItem *__restrict__ items,
+                                            int64_t cap_arg, const WorkItem *__restrict__ items,
                                             const uint32_t *__restrict__ n_items, GNode *__restrict__ gout,
                                             uint32_t *__restrict__ flags, uint64_t *stats) {
     const DevParams &P = params_ref(Parg);
+    const int64_t cap = cap_ref(cap_arg);
     constexpr int TN = Geo<DIM>::TN, D2 = DIM * DIM;
     __shared__ unsigned long long acc[4 * TN];
     __shared__ uint32_t touched[27];
@@ -448,12 +449,13 @@ __device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int n
 
 template <int DIM, bool RS, int MAT>
 __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevScheme *__restrict__ sch, DevParams Parg, uint32_t *words,
-                                                int64_t cap, const WorkItem *__restrict__ items,
+                                                int64_t cap_arg, const WorkItem *__restrict__ items,
                                                 const uint32_t *__restrict__ n_items,
                                                 const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
                                                 uint32_t *__restrict__ flags, uint32_t step, int do_p2g,
                                                 int collect_stats, uint64_t *stats) {
     const DevParams &P = params_ref(Parg);
+    const int64_t cap = cap_ref(cap_arg);
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
     __shared__ float gv[DIM * TN];
     __shared__ unsigned long long acc[4 * TN];
