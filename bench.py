@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-substeps/s and bytes/particle, quantized vs FP32 layout, at 1e-4 pos error"
 HBM_PEAK_GBS = 8000.0
+# the fused kernel's sources, and the run-time specialization that compiles it
 KERNEL_SOURCES = ["paper_2207_04658_amd/csrc/substep.hpp", "paper_2207_04658_amd/csrc/mpmq_device.hpp",
-                  "paper_2207_04658_amd/csrc/mpmq_internal.hpp"]
+                  "paper_2207_04658_amd/csrc/mpmq_internal.hpp", "paper_2207_04658_amd/csrc/jit.hip"]
 
 
 def log(msg):
