@@ -206,7 +206,7 @@ __device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, doub
     // clamp to [0, maxc] (fmax takes a NaN to 0); a value the clamp changed
     // saturated.  Selects rather than branches: the counters are per-lane.
     const bool nan = !(sv == sv), below = fl < 0.0, above = fl > f->maxc;
-    const uint32_t code = (nan || below) ? 0u : above ? (uint32_t)f->maxc : (uint32_t)fl;
+    const uint32_t code = (uint32_t)fmin(fmax(fl, 0.0), f->maxc);  // fmax takes a NaN to 0
     ls.nan += nan ? 1u << (8 * fid) : 0u;
     ls.sat += (below || above) ? 1u << (8 * fid) : 0u;
     if (RS) ls.ud[fid] += (nan || below || above) ? 0u : (fl > floor(t)) ? 1u : 0x10000u;
