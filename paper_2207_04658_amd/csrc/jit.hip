@@ -48,7 +48,8 @@ std::string initializer(const DevScheme &d) {
         s += "{" + std::to_string(f.kind) + ", " + std::to_string(f.bits) + ", " + std::to_string(f.exp_bits) + ", " +
              std::to_string(f.dither) + ", " + std::to_string(f.rel) + ", " + std::to_string(f.off) + ", " +
              std::to_string(f.emin) + ", " + std::to_string(f.emax) + ", " + std::to_string(f.mask) + "u, " +
-             std::to_string(f.exp_mask) + "u, " + std::to_string(f.mag_mask) + "u, 0u, " + hexd(f.lo) + ", " +
+             std::to_string(f.exp_mask) + "u, " + std::to_string(f.mag_mask) + "u, " + std::to_string(f.f32dec) +
+             "u, " + hexd(f.lo) + ", " +
              hexd(f.delta) + ", " + hexd(f.inv) + ", " + hexd(f.maxc) + "}" + (i < 3 ? ", " : "}}");
     }
     return s;

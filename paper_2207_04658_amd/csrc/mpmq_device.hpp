@@ -31,6 +31,18 @@ typedef const __attribute__((address_space(4))) DevField *FieldRef;
 __device__ __forceinline__ SchemeRef seed_ref(const DevScheme *p) { return (SchemeRef)opaque(p); }
 // The same holds for the simulation parameters (MPMQ_PARAMS_CONST, a
 // DevParams initializer): a context's parameters never change.
+// Float32 decode: with the scheme fixed at compile time, a field whose
+// decoded values are all exact in float32 (DevField::f32dec) is decoded in
+// float32 arithmetic, which then gives the same values as the binary64
+// formula rounded once.
+#ifdef MPMQ_SCHEME_CONST
+constexpr bool kF32Decode = true;
+#else
+constexpr bool kF32Decode = false;
+#endif
+template <typename T> struct is_f32 { static constexpr bool value = false; };
+template <> struct is_f32<float> { static constexpr bool value = true; };
+
 // ... and for the row stride of the packed words (MPMQ_CAP_CONST): with a
 // constant stride the row addresses need no registers.
 #ifdef MPMQ_CAP_CONST
@@ -262,8 +274,13 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
         if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
         os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);
-        const double mag = ldexp((double)qc, E - m1);
-        qv[c] = (T)(neg ? -mag : mag);
+        if (kF32Decode && is_f32<T>::value && f->f32dec) {
+            const float mag = ldexpf((float)qc, E - m1);
+            qv[c] = (T)(neg ? -mag : mag);
+        } else {
+            const double mag = ldexp((double)qc, E - m1);
+            qv[c] = (T)(neg ? -mag : mag);
+        }
     }
 }
 
@@ -284,8 +301,13 @@ __device__ __forceinline__ void enc_field(const FieldRef f, const T *val, Draws 
             const double h = f->dither ? dither_h(rnd, K0 + c) : XI_HALF;
             const uint32_t code = enc_fixed<RS>(f, rel, h, slot_of<FID>(), ls);
             os.emit(code, f->bits);
-            const double q = fma((double)code, f->delta, f->lo);
-            qv[c] = (T)(diag ? q + 1.0 : q);
+            if (kF32Decode && is_f32<T>::value && f->f32dec) {
+                const float q = fmaf((float)code, (float)f->delta, (float)f->lo);
+                qv[c] = (T)(diag ? q + 1.0f : q);
+            } else {
+                const double q = fma((double)code, f->delta, f->lo);
+                qv[c] = (T)(diag ? q + 1.0 : q);
+            }
         }
     } else if (f->kind == K_RAW) {
 #pragma unroll
@@ -310,8 +332,15 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
     if (f->kind == K_FIXED) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double q = fma((double)get_comp(words, cap, p4, f->off + c * f->bits, f->bits, f->mask), f->delta, f->lo);
-            out[c] = (T)((f->rel && (c % (DIM + 1) == 0)) ? q + 1.0 : q);
+            const uint32_t u = get_comp(words, cap, p4, f->off + c * f->bits, f->bits, f->mask);
+            const bool diag = f->rel && (c % (DIM + 1) == 0);
+            if (kF32Decode && is_f32<T>::value && f->f32dec) {
+                const float q = fmaf((float)u, (float)f->delta, (float)f->lo);
+                out[c] = (T)(diag ? q + 1.0f : q);
+            } else {
+                const double q = fma((double)u, f->delta, f->lo);
+                out[c] = (T)(diag ? q + 1.0 : q);
+            }
         }
     } else if (f->kind == K_RAW) {
 #pragma unroll
@@ -326,8 +355,13 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const uint32_t q = get_comp(words, cap, p4, o0 + c * f->bits, f->bits, f->mask);
-            const double mag = ldexp((double)(q & f->mag_mask), E - m1);
-            out[c] = (T)(((q >> m1) & 1u) ? -mag : mag);
+            if (kF32Decode && is_f32<T>::value && f->f32dec) {
+                const float mag = ldexpf((float)(q & f->mag_mask), E - m1);
+                out[c] = (T)(((q >> m1) & 1u) ? -mag : mag);
+            } else {
+                const double mag = ldexp((double)(q & f->mag_mask), E - m1);
+                out[c] = (T)(((q >> m1) & 1u) ? -mag : mag);
+            }
         }
     }
 }

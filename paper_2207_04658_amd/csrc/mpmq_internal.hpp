@@ -43,7 +43,8 @@ constexpr int MAX_WORDS = 32;    // record <= 1024 bits
 struct DevField {
     int32_t kind, bits, exp_bits, dither;
     int32_t rel, off, emin, emax;        // off: first record bit (SHARED_EXP: exponent)
-    uint32_t mask, exp_mask, mag_mask, pad0;
+    uint32_t mask, exp_mask, mag_mask;
+    uint32_t f32dec;                     // 1: every decoded value is exact in float32 (see compile_scheme)
     double lo, delta, inv, maxc;         // FIXED: range start, step, 2^b/(hi-lo), 2^b-1
 };
 

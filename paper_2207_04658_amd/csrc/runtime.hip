@@ -76,6 +76,15 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
             d.delta = std::ldexp(f.hi - f.lo, -f.bits);
             d.inv = std::ldexp(1.0, f.bits) / (f.hi - f.lo);
             d.maxc = std::ldexp(1.0, f.bits) - 1.0;
+            // decoded values lo + u delta (+ 1 on a REL_IDENTITY diagonal) are
+            // exact in float32 when delta is a power of two in [2^-100, 1], lo
+            // is a multiple of it and every value is below 2^24 delta
+            int e = 0;
+            const bool pow2 = std::frexp(d.delta, &e) == 0.5 && d.delta >= std::ldexp(1.0, -100) && d.delta <= 1.0;
+            const double top = std::ldexp(d.delta, 24), last = d.lo + d.maxc * d.delta;
+            bool fits = f.bits <= 24 && std::fabs(d.lo) < top && std::fabs(last) < top;
+            if (rel) fits = fits && std::fabs(d.lo + 1.0) < top && std::fabs(last + 1.0) < top;
+            d.f32dec = (pow2 && std::fmod(d.lo, d.delta) == 0.0 && fits) ? 1u : 0u;
         } else if (f.kind == MPMQ_SHARED_EXP) {
             if (f.bits < 2 || f.bits > 32) { err = std::string("field ") + nm + ": SHARED_EXP bits must be in [2, 32]"; return false; }
             if (f.exp_bits < 1 || f.exp_bits > 8) { err = std::string("field ") + nm + ": exp_bits must be in [1, 8]"; return false; }
@@ -84,6 +93,8 @@ bool compile_scheme(const mpmq_scheme *sc, DevScheme &ds, int &total_bits, std::
             d.emin = d.emax - ((1 << f.exp_bits) - 1);
             d.mag_mask = (uint32_t)((1ull << (f.bits - 1)) - 1ull);
             d.exp_mask = (uint32_t)((1ull << f.exp_bits) - 1ull);
+            // q 2^(E - m + 1) is exact in float32 for q < 2^24 and normal exponents
+            d.f32dec = (f.bits - 1 <= 24 && d.emin - (f.bits - 1) >= -126 && d.emax <= 127) ? 1u : 0u;
             off += f.exp_bits;
         } else if (f.kind == MPMQ_RAW_F32) {
             if (f.bits != 32) { err = std::string("field ") + nm + ": RAW_F32 bits must be 32"; return false; }
