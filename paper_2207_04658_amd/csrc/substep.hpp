@@ -354,11 +354,19 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
 // ---------------------------------------------------------------------------
 
 // G2P from the LDS tile, separable in the three axes:
-// v' = sum_i w v_i and S_b = sum_i w (o_b - f_b) v_i, C' = 4/dx S.
+// v' = sum_i w v_i and S_b = sum_i w (o_b - f_b) v_i, C' = 4/dx S, computed as
+// S_b = sum_i w o_b v_i - f_b v' (o_b in {0, 1, 2}: the o_b = 0 terms drop out).
 template <int DIM>
 __device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, const float (*wx)[3],
-                                         const float (*wd)[3], float *nv, float (*S)[DIM]) {
+                                         const float *fx, float *nv, float (*S)[DIM]) {
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN;
+    float wo[DIM][3];  // o w_o
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        wo[a][0] = 0.0f;
+        wo[a][1] = wx[a][1];
+        wo[a][2] = 2.0f * wx[a][2];
+    }
     if constexpr (DIM == 3) {
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
@@ -373,13 +381,13 @@ __device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, c
                     for (int a = 0; a < 3; ++a) {
                         const float vi = gv[a * TN + idx];
                         R0[a] += wx[0][ox] * vi;
-                        R1[a] += wd[0][ox] * vi;
+                        if (ox > 0) R1[a] += wo[0][ox] * vi;
                     }
                 }
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     P00[a] += wx[1][oy] * R0[a];
-                    P01[a] += wd[1][oy] * R0[a];
+                    if (oy > 0) P01[a] += wo[1][oy] * R0[a];
                     P10[a] += wx[1][oy] * R1[a];
                 }
             }
@@ -388,7 +396,7 @@ __device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, c
                 nv[a] += wx[2][oz] * P00[a];
                 S[0][a] += wx[2][oz] * P10[a];
                 S[1][a] += wx[2][oz] * P01[a];
-                S[2][a] += wd[2][oz] * P00[a];
+                if (oz > 0) S[2][a] += wo[2][oz] * P00[a];
             }
         }
     } else {
@@ -402,17 +410,21 @@ __device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, c
                 for (int a = 0; a < 2; ++a) {
                     const float vi = gv[a * TN + idx];
                     R0[a] += wx[0][ox] * vi;
-                    R1[a] += wd[0][ox] * vi;
+                    if (ox > 0) R1[a] += wo[0][ox] * vi;
                 }
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 nv[a] += wx[1][oy] * R0[a];
                 S[0][a] += wx[1][oy] * R1[a];
-                S[1][a] += wd[1][oy] * R0[a];
+                if (oy > 0) S[1][a] += wo[1][oy] * R0[a];
             }
         }
     }
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) S[b][a] -= fx[b] * nv[a];
 }
 
 // G2P straight from the grid buffer, for a particle whose stencil left its tile.
@@ -492,15 +504,13 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             dec_field<DIM, 0, double>(&sp->f[0], words, cap, p4, xd);
             dec_field<DIM, fid3<MAT>(), float>(&sp->f[3], words, cap, p4, F);
             int base[DIM];
-            float fx[DIM], wx[DIM][3], wd[DIM][3];
+            float fx[DIM], wx[DIM][3];
             stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
             bool in_tile = true;
             int l[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 bspline(fx[a], wx[a]);
-#pragma unroll
-                for (int o = 0; o < 3; ++o) wd[a][o] = wx[a][o] * ((float)o - fx[a]);
                 l[a] = base[a] - origin[a];
                 in_tile &= (l[a] >= 0) && (l[a] <= TB - 3);
             }
@@ -513,9 +523,14 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             }
             if (in_tile) {
                 const int l0 = (DIM == 3) ? (l[DIM - 1] * TB + l[1]) * TB + l[0] : l[1] * TB + l[0];
-                g2p_tile<DIM>(gv, l0, wx, wd, nv, S);
+                g2p_tile<DIM>(gv, l0, wx, fx, nv, S);
             } else {
                 fallback += 1;
+                float wd[DIM][3];  // w (o - f)
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) wd[a][o] = wx[a][o] * ((float)o - fx[a]);
                 g2p_global<DIM>(gcur, P.nb, base, wx, wd, nv, S);
             }
             // update: x' = x + dt v' (binary64), C' = 4/dx S, F' = (I + dt C') F
