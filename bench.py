@@ -299,7 +299,7 @@ def bench_adjoint(a):
     T = sc["steps"]
     res = {}
     for K in (8, 0):
-        ctx = mq.Context(sc["scheme"], sc["params"], sc["n"])
+        ctx = mq.Context(sc["scheme"], sc["params"], sc["n"], specialize=not a.generic)
         ts = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in sc["state"]]
         ctx.encode(*ts)
         ctx.adjoint(2, objective="ke", checkpoint_every=K)  # warm-up
@@ -335,6 +335,7 @@ def bench_adjoint(a):
         "states_held": {"checkpoint_every_8": r8["states"], "bisection": res[0][1]["states"]},
         "recomputed_substeps": {"checkpoint_every_8": r8["recomputed"], "bisection": res[0][1]["recomputed"]},
         "g": r8["g"],
+        "kernels_specialized": not a.generic,
         "cpu_baseline": {"value": round(cpu_rate, 1), "unit": "particle-substeps/s (backward only)", "cores": 1,
                          "kind": "oracle", "sample": "orc_step_vjp on the 16^3 version of the scene (4096 particles)"},
     }

@@ -472,9 +472,10 @@ template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_reduce(const float *__restrict__ lam, int64_t n,
                                                    double *__restrict__ acc) {
     constexpr int LR = LROWS<DIM, MAT>();
-    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     double G[4] = {0, 0, 0, 0}, g[4] = {0, 0, 0, 0};
-    if (p < n) {
+    // grid-stride (a few hundred groups), then wave and group sums: one
+    // atomic per sum and group (atomics on one address serialize in the L2)
+    for (int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x; p < n; p += (int64_t)gridDim.x * WG) {
 #pragma unroll
         for (int r = 0; r < LR; ++r) {
             const int f = r < DIM ? 0 : r < 2 * DIM ? 1 : r < 2 * DIM + DIM * DIM ? 2 : 3;
@@ -491,12 +492,20 @@ __global__ __launch_bounds__(WG) void k_adj_reduce(const float *__restrict__ lam
             g[f] += __shfl_xor(g[f], o, 64);
         }
     }
+    __shared__ double part[WG / 64][8];
     if (__lane_id() == 0) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            atomicAdd(acc + 1 + f, G[f]);
-            atomicAdd(acc + 5 + f, g[f]);
+            part[threadIdx.x >> 6][f] = G[f];
+            part[threadIdx.x >> 6][4 + f] = g[f];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < WG / 64; ++w) t += part[w][threadIdx.x];
+        atomicAdd(acc + 1 + threadIdx.x, t);  // acc[1..4]: sums, acc[5..8]: sums of squares
     }
 }
 
@@ -518,9 +527,8 @@ template <int DIM, int MAT>
 __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ sch, const uint32_t *__restrict__ words,
                                                   int64_t cap, int64_t n, uint32_t *__restrict__ rng) {
     constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
-    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
     uint32_t lo[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[4] = {0u, 0u, 0u, 0u};
-    if (p < n) {
+    for (int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x; p < n; p += (int64_t)gridDim.x * WG) {
         SchemeRef s = scheme_ref(sch);
         const uint32_t p4 = (uint32_t)p * 4u;
         double xd[DIM];
@@ -558,12 +566,21 @@ __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ 
             hi[f] = max(hi[f], (uint32_t)__shfl_xor((int)hi[f], o, 64));
         }
     }
+    __shared__ uint32_t part[WG / 64][8];
     if (__lane_id() == 0) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            atomicMin(rng + f, lo[f]);
-            atomicMax(rng + 4 + f, hi[f]);
+            part[threadIdx.x >> 6][f] = lo[f];
+            part[threadIdx.x >> 6][4 + f] = hi[f];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        uint32_t t = part[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < WG / 64; ++w) t = (threadIdx.x < 4) ? min(t, part[w][threadIdx.x]) : max(t, part[w][threadIdx.x]);
+        if (threadIdx.x < 4) atomicMin(rng + threadIdx.x, t);
+        else atomicMax(rng + threadIdx.x, t);  // rng[4..7]: maxima
     }
 }
 
@@ -579,6 +596,8 @@ __global__ void k_adj_unpermute(const float *__restrict__ lam, const uint32_t *_
 }
 
 static dim3 agrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
+// reductions: at most 256 groups (grid-stride), one atomic per group and sum
+static dim3 rgrid(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + WG - 1) / WG, 256)); }
 
 #define MPMQ_ADJ_DISPATCH(KERNEL, GRID, ...)                                                              \
     do {                                                                                                 \
@@ -608,14 +627,14 @@ hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams
 }
 
 hipError_t launch_adj_reduce(int dim, int mat, const float *lam, int64_t n, double *acc, hipStream_t st) {
-    MPMQ_ADJ_DISPATCH(k_adj_reduce, agrid(n), lam, n, acc);
+    MPMQ_ADJ_DISPATCH(k_adj_reduce, rgrid(n), lam, n, acc);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_range(int dim, int mat, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n,
                             uint32_t *rng, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    MPMQ_ADJ_DISPATCH(k_adj_range, agrid(n), s, words, cap, n, rng);
+    MPMQ_ADJ_DISPATCH(k_adj_range, rgrid(n), s, words, cap, n, rng);
     return hipGetLastError();
 }
 
