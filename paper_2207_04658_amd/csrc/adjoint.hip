@@ -8,7 +8,7 @@
 // Adjoint state layout: float32 SoA, L = 2d + 2d^2 rows of n:
 // x[d], v[d], C[d*d], F[d*d].  Node adjoints: float4 per node (the grid's
 // block-major node order).
-#include "mpmq_device.hpp"
+#include "substep.hpp"  // tile helpers, work-item walk (includes mpmq_device.hpp)
 
 namespace mpmq {
 
@@ -154,16 +154,18 @@ __device__ __forceinline__ void stencil_all(const DevParams &P, const double *xd
     }
 }
 
-// G2P backward: from lambda_{t+1} (of x', v', C', F') to the partial lambda_t
-// of x and F, and the node adjoints lambda_v_i (scattered with atomics).
+// G2P backward of particle p: from lambda_{t+1} (of x', v', C', F') to the
+// partial lambda_t of x and F, and the node adjoints lambda_v_i, added into
+// the LDS tile `tacc` (3 x TN floats, tile corner `origin`) when the
+// particle's stencil lies in it, else into the grid-wide `nadj` with atomics.
 template <int DIM, int MAT>
-__global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sch, DevParams P,
-                                                const uint32_t *__restrict__ words, int64_t cap, int64_t n,
-                                                const GNode *__restrict__ grid, const float *__restrict__ lin,
-                                                float *__restrict__ lout, float4 *__restrict__ nadj) {
+__device__ __forceinline__ void adj_g2p_particle(const DevScheme *__restrict__ sch, const DevParams &P,
+                                                 const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                 int64_t p, const GNode *__restrict__ grid,
+                                                 const float *__restrict__ lin, float *__restrict__ lout,
+                                                 float4 *__restrict__ nadj, float *tacc, const int *origin) {
     constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST, N3 = nc3<DIM, MAT>();
-    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (p >= n) return;
+    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN;
     SchemeRef s = scheme_ref(sch);
     const uint32_t p4 = (uint32_t)p * 4u;
     double xd[DIM];
@@ -173,6 +175,14 @@ __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sc
     int base[DIM];
     float fx[DIM], w[DIM][3], dw[DIM][3];
     stencil_all<DIM>(P, xd, base, fx, w, dw);
+    bool in_tile = true;
+    int l0 = 0;
+#pragma unroll
+    for (int a = DIM - 1; a >= 0; --a) {
+        const int la = base[a] - origin[a];
+        in_tile &= (la >= 0) && (la <= TB - 3);
+        l0 = l0 * TB + la;
+    }
     const float D = 4.0f * P.inv_dx * P.inv_dx;
     // recompute C' for the F' adjoint
     float Cn[D2];
@@ -261,12 +271,14 @@ __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sc
         const float vi[3] = {g.x, g.y, g.z};
         float lw = 0.0f;
         float *na = reinterpret_cast<float *>(nadj + id);
+        const int lt = l0 + ((DIM == 3) ? (o[2] * TB + o[1]) * TB + o[0] : o[1] * TB + o[0]);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             float ld = 0.0f;
 #pragma unroll
             for (int b = 0; b < DIM; ++b) ld += lC[a * DIM + b] * d[b];
-            unsafeAtomicAdd(na + a, wt * (lv[a] + D * ld));
+            if (in_tile) atomicAdd(&tacc[a * TN + lt], wt * (lv[a] + D * ld));
+            else unsafeAtomicAdd(na + a, wt * (lv[a] + D * ld));
             lw += lv[a] * vi[a] + D * vi[a] * ld;
 #pragma unroll
             for (int b = 0; b < DIM; ++b) ox[b] -= D * wt * lC[a * DIM + b] * vi[a];
@@ -283,6 +295,43 @@ __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sc
     for (int c = 0; c < D2; ++c) lout[(2 * DIM + c) * n + p] = 0.0f;
 #pragma unroll
     for (int c = 0; c < N3; ++c) lout[(2 * DIM + D2 + c) * n + p] = oF[c];
+}
+
+// Per work item (the forward's sort): node adjoints of the item's particles
+// accumulate in an LDS tile, which is then added to `nadj` with one atomic
+// per non-zero node component.
+template <int DIM, int MAT>
+__global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sch, DevParams P,
+                                                const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                const WorkItem *__restrict__ items,
+                                                const uint32_t *__restrict__ n_items,
+                                                const GNode *__restrict__ grid, const float *__restrict__ lin,
+                                                float *__restrict__ lout, float4 *__restrict__ nadj) {
+    constexpr int TN = Geo<DIM>::TN;
+    __shared__ float tacc[3 * TN];
+    const uint32_t nit = *n_items;
+    const ItemWalk walk(nit);
+    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
+        const WorkItem it = items[item];
+        int origin[DIM];
+        tile_origin<DIM>(it.block, P.nb, origin);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 3 * TN; t += WG) tacc[t] = 0.0f;
+        __syncthreads();
+        for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += WG)
+            adj_g2p_particle<DIM, MAT>(sch, P, words, cap, n, p, grid, lin, lout, nadj, tacc, origin);
+        __syncthreads();
+        // lanes take (node, component) pairs: adjacent lanes, adjacent words
+        for (int q = threadIdx.x; q < 4 * TN; q += WG) {
+            const int t = q >> 2, c = q & 3;
+            if (c >= DIM) continue;
+            const float v = tacc[c * TN + t];
+            if (v == 0.0f) continue;
+            int ijk[DIM];
+            if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached: stencils stay in-grid
+            unsafeAtomicAdd(reinterpret_cast<float *>(nadj + node_index<DIM>(ijk, P.nb)) + c, v);
+        }
+    }
 }
 
 // Grid backward: v_i = mom_i / m_i + dt g (components zeroed by the wall
@@ -615,11 +664,13 @@ hipError_t launch_adj_objective(int dim, int mat, const DevScheme *s, const DevP
 }
 
 hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words,
-                           int64_t cap, int64_t n, const GNode *grid, int64_t nodes, const float *lin, float *lout,
-                           float4 *nadj, hipStream_t st) {
+                           int64_t cap, int64_t n, const WorkItem *items, const uint32_t *n_items, int item_grid,
+                           const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
+                           hipStream_t st) {
     hipLaunchKernelGGL(k_zero_f4, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 65536)), dim3(256), 0, st,
                        nadj, nodes);
-    MPMQ_ADJ_DISPATCH(k_adj_g2p, agrid(n), s, P, words, cap, n, grid, lin, lout, nadj);
+    MPMQ_ADJ_DISPATCH(k_adj_g2p, dim3((unsigned)item_grid), s, P, words, cap, n, items, n_items, grid, lin, lout,
+                      nadj);
     if (dim == 3) hipLaunchKernelGGL(k_adj_grid<3>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
     else hipLaunchKernelGGL(k_adj_grid<2>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
     MPMQ_ADJ_DISPATCH(k_adj_p2g, agrid(n), s, P, words, cap, n, nadj, lout);
