@@ -342,3 +342,33 @@ def test_alg1_memory_bounded_scheme(gpu_lib):
     zq = q.adjoint(T, objective="ke", checkpoint_every=0)["z"]
     q.close()
     assert math.isfinite(zq) and abs(zq - ref["z"]) <= 0.05 * abs(ref["z"]), (zq, ref["z"])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adjoint_tile_fallback_vs_oracle(gpu_lib, orc, dim):
+    """A fast cube, sorted once: stencils leave the node tiles of their sort
+    blocks, so the forward and the G2P backward also take their grid-wide
+    atomic paths; lambda_0, G and g still match the oracle."""
+    # 2D node blocks are 16 cells wide: a finer grid, so that there are several
+    res, T = (64, 8) if dim == 2 else (16, 8)
+    dt = 5e-4 if dim == 2 else 1e-3
+    side = 6 / res
+    # just above a node-block boundary, moving towards it
+    corners = np.array([[0.26, 0.27]]) if dim == 2 else np.array([[0.35, 0.4, 0.35]])
+    vels = np.array([[-17.0, -11.0, -14.0]])[:, :dim]
+    scheme = WL.scheme_c1(dim, True, 4)
+    scene = WL.cubes_scene("fast", 4, res, corners, side, [8 * 6 ** dim], vels, dt, T, scheme, 0, dim=dim)
+    note(f"adjoint tile fallback dim={dim} n={scene['n']} T={T}")
+    ctx = gpu_context(gpu_lib, scene)
+    res_g = ctx.adjoint(T, objective="ke", axis=1, checkpoint_every=3, want_lambda0=True)
+    st = ctx.stats()
+    assert st["fallback"] > 0 and st["sorts"] == 1, st
+    lg = res_g["lambda0"].cpu().numpy().astype(np.float64)
+    states = oracle_trajectory(orc, scene, T)
+    z, G, g, A, lo = orc.adjoint_full(scene["params"], states, "ke", 1)
+    assert math.isclose(res_g["z"], z, rel_tol=2e-3), (res_g["z"], z)
+    steps = field_steps(scene["scheme"])
+    assert_weighted_close(split_lambda(lg, dim), split_lambda(lo, dim), steps, 2e-2, "lambda_0")
+    assert_weighted_close(res_g["g"], g, steps, 3e-2, "g", power=2)
+    assert_weighted_close(res_g["G"], G, steps, 2e-2, "G")
+    ctx.close()

@@ -232,3 +232,40 @@ def test_step_before_encode_is_state_error(gpu_lib):
         ctx.adjoint(1)
     assert e.value.status == -4
     ctx.close()
+
+
+def fast_scene(dim, seed, vmax):
+    """small_scene with particles fast enough to leave the node tile of
+    their sort block (sorted once: sort_every = 0)."""
+    sc = small_scene(dim, seed, True, 0)
+    x, v, C, F = sc["state"]
+    v = np.clip(v * (vmax / max(1e-6, float(np.max(np.abs(v))))), -vmax, vmax).astype(np.float32)
+    sc["state"] = (x, v, C, F)
+    return sc
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tile_fallback_trajectory(gpu_lib, orc, dim):
+    """Stencils that left their tile go through the global P2G / G2P paths
+    (int64 atomics straight into the grid): same trajectory as the oracle,
+    and as the GPU with a sort every substep (no stencil leaves a tile)."""
+    sc = fast_scene(dim, 21 + dim, 18.0)
+    steps = 16
+    note(f"tile fallback dim={dim} n={sc['n']} steps={steps}")
+    ctx = gpu_context(gpu_lib, sc)
+    ctx.step(steps)
+    st = ctx.stats()
+    assert st["sorts"] == 1 and st["fallback"] > 0, st
+    resorted = dict(sc, params=dict(sc["params"], sort_every=1))
+    ctx1 = gpu_context(gpu_lib, resorted)
+    ctx1.step(steps)
+    assert ctx1.stats()["sorts"] == steps
+    sim, _, _ = oracle_sim(orc, sc)
+    sim.step(steps)
+    gx = by_id(gpu_decode_np(ctx)[0], ctx.ids())
+    gx1 = by_id(gpu_decode_np(ctx1)[0], ctx1.ids())
+    ox = by_id(orc.decode(sc["scheme"], sim.words())[0], sim.ids())
+    assert np.max(np.abs(gx - ox)) <= 1e-4, np.max(np.abs(gx - ox))
+    assert np.max(np.abs(gx - gx1)) <= 1e-4, np.max(np.abs(gx - gx1))
+    ctx.close()
+    ctx1.close()
