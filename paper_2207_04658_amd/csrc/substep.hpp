@@ -248,11 +248,40 @@ __device__ __forceinline__ bool tile_node(int t, const int *origin, int res, int
 // before, the next BLK in its own block, the rest in the block after.  The
 // flags go through `touched` (LDS, 3^DIM entries, zero on entry and on
 // return): one global store per touched block instead of one per node.
+// Neighbour-block code of tile node t: (l == 0 ? 0 : l <= BLK ? 1 : 2) per
+// axis, last axis most significant.
+template <int DIM>
+__device__ __forceinline__ int tile_block_code(const int *ijk, const int *origin) {
+    constexpr int B = Geo<DIM>::BLK;
+    int k = 0;
+#pragma unroll
+    for (int a = DIM - 1; a >= 0; --a) {
+        const int l = ijk[a] - origin[a];  // 0 .. TB-1
+        k = 3 * k + ((l == 0) ? 0 : (l <= B) ? 1 : 2);
+    }
+    return k;
+}
+
+// `table` (optional LDS scratch of TN words + TN bytes, free at the flush):
+// the grid index and block code of every tile node are computed once, not
+// once per component.
 template <int DIM>
 __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin,
                                            const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
-                                           uint32_t *__restrict__ flags, uint32_t *touched) {
+                                           uint32_t *__restrict__ flags, uint32_t *touched,
+                                           uint32_t *__restrict__ table = nullptr) {
     constexpr int TN = Geo<DIM>::TN, TB = Geo<DIM>::TB, B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
+    unsigned char *code = reinterpret_cast<unsigned char *>(table + TN);
+    if (table) {
+        // node index < 1024^3 fits 32 bits; 0xffffffff: outside the grid
+        for (int t = threadIdx.x; t < TN; t += PWG) {
+            int ijk[DIM];
+            const bool ok = tile_node<DIM>(t, origin, P.res, ijk);
+            table[t] = ok ? (uint32_t)node_index<DIM>(ijk, P.nb) : 0xffffffffu;
+            code[t] = (unsigned char)tile_block_code<DIM>(ijk, origin);
+        }
+        __syncthreads();
+    }
     // lane q takes component q % 4 of tile node q / 4: the four sums of a
     // node are adjacent in memory, so one wave-wide atomic instruction
     // covers whole cache lines (16 nodes) instead of 64 scattered words
@@ -260,16 +289,17 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
         const int t = q >> 2, c = q & 3;
         const unsigned long long sum = acc[c * TN + t];
         if (sum != 0ull) {
-            int ijk[DIM];
-            if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached: contributions stay in-grid
-            atomicAdd(gout[node_index<DIM>(ijk, P.nb)].q + c, sum);
-            int k = 0;
-#pragma unroll
-            for (int a = DIM - 1; a >= 0; --a) {
-                const int l = ijk[a] - origin[a];  // 0 .. TB-1
-                k = 3 * k + ((l == 0) ? 0 : (l <= B) ? 1 : 2);
+            if (table) {
+                const uint32_t id = table[t];
+                if (id == 0xffffffffu) continue;  // never reached: contributions stay in-grid
+                atomicAdd(gout[id].q + c, sum);
+                touched[code[t]] = 1u;
+            } else {
+                int ijk[DIM];
+                if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached, as above
+                atomicAdd(gout[node_index<DIM>(ijk, P.nb)].q + c, sum);
+                touched[tile_block_code<DIM>(ijk, origin)] = 1u;
             }
-            touched[k] = 1u;
         }
     }
     static_assert(TB - 1 - B <= B, "a tile spans at most three blocks per axis");
@@ -573,7 +603,9 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             if (do_p2g) p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
         }
         __syncthreads();
-        if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags, touched);
+        // the velocity tile is free now: it holds the flush's node table
+        static_assert(DIM * TN * sizeof(float) >= TN * (sizeof(uint32_t) + 1), "node table fits the velocity tile");
+        if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags, touched, reinterpret_cast<uint32_t *>(gv));
         if (collect_stats) {
             flush_stats(ls, stats);
             ls.clear();
