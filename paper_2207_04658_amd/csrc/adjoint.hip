@@ -199,7 +199,7 @@ __device__ __forceinline__ void adj_g2p_particle(const DevScheme *__restrict__ s
             wt *= w[a][o[a]];
             d[a] = ((float)o[a] - fx[a]) * P.dx;
         }
-        const float4 g = reinterpret_cast<const float4 *>(grid + node_index<DIM>(ijk, P.nb))[0];
+        const float4 g = node_vel<DIM>(grid, node_index<DIM>(ijk, P.nb));
         const float vi[3] = {g.x, g.y, g.z};
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
@@ -267,7 +267,7 @@ __device__ __forceinline__ void adj_g2p_particle(const DevScheme *__restrict__ s
                 if (b != a) gw[a] *= w[b][o[b]];
         }
         const int64_t id = node_index<DIM>(ijk, P.nb);
-        const float4 g = reinterpret_cast<const float4 *>(grid + id)[0];
+        const float4 g = node_vel<DIM>(grid, id);
         const float vi[3] = {g.x, g.y, g.z};
         float lw = 0.0f;
         float *na = reinterpret_cast<float *>(nadj + id);
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(WG) void k_adj_grid(DevParams P, const GNode *__res
     constexpr int B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
     const int64_t id = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (id >= nodes) return;
-    const float4 g = reinterpret_cast<const float4 *>(grid + id)[0];
+    const float4 g = node_vel<DIM>(grid, id);
     const float4 la = nadj[id];
     float out[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     const float m = g.w;  // physical node mass (0: no particle touched it)

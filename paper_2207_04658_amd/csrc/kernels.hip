@@ -406,6 +406,8 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restri
             GNode g[CPB / WG];
 #pragma unroll
             for (int r = 0; r < CPB / WG; ++r) g[r] = gcur[(b << (DIM * L)) + threadIdx.x + r * WG];
+            // the packed velocities overwrite the first half of the block
+            __syncthreads();
 #pragma unroll
             for (int r = 0; r < CPB / WG; ++r) {
                 const int l = threadIdx.x + r * WG;
@@ -426,7 +428,8 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restri
                     }
                 }
                 const float mass = m > 0.0 ? (float)(m * (1.0 / FIX_ONE)) * P.p_mass : 0.0f;
-                reinterpret_cast<float4 *>(gcur + (b << (DIM * L)) + l)[0] = make_float4(vel[0], vel[1], vel[2], mass);
+                reinterpret_cast<float4 *>(gcur)[vel_slot<DIM>((b << (DIM * L)) + l)] =
+                    make_float4(vel[0], vel[1], vel[2], mass);
             }
         }
         if (tn) {

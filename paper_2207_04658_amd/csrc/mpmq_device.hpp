@@ -407,6 +407,19 @@ __device__ __forceinline__ void encode_record(const DevScheme *sp, const double 
 // MLS-MPM helpers (quadratic B-spline, fixed-corotated elasticity).
 // ---------------------------------------------------------------------------
 
+// After the grid update a node block's storage (BLK^DIM GNodes of 32 B)
+// holds the blocks's node velocities and masses as float4, packed into its
+// first half: node l of the block in float4 slot l.  Node index id ->
+// float4 index in the grid buffer.  Tile loads then use whole cache lines.
+template <int DIM>
+__device__ __forceinline__ int64_t vel_slot(int64_t id) {
+    return id + (id & ~(int64_t)(Geo<DIM>::CPB - 1));
+}
+template <int DIM>
+__device__ __forceinline__ float4 node_vel(const GNode *__restrict__ grid, int64_t id) {
+    return reinterpret_cast<const float4 *>(grid)[vel_slot<DIM>(id)];
+}
+
 // Block-major node index: node blocks of BLK^DIM nodes, nb blocks per axis.
 template <int DIM>
 __device__ __forceinline__ int64_t node_index(const int *ijk, int nb) {

@@ -473,7 +473,7 @@ __device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int n
             ijk[a] = base[a] + o[a];
             w *= wx[a][o[a]];
         }
-        const float4 g = reinterpret_cast<const float4 *>(gcur + node_index<DIM>(ijk, nb))[0];
+        const float4 g = node_vel<DIM>(gcur, node_index<DIM>(ijk, nb));
         const float vi[3] = {g.x, g.y, g.z};
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             int ijk[DIM];
             float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (tile_node<DIM>(t, origin, P.res, ijk))
-                g = reinterpret_cast<const float4 *>(gcur + node_index<DIM>(ijk, P.nb))[0];
+                g = node_vel<DIM>(gcur, node_index<DIM>(ijk, P.nb));
             gv[t] = g.x;
             gv[TN + t] = g.y;
             if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
