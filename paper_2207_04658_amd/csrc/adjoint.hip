@@ -12,6 +12,9 @@
 
 namespace mpmq {
 
+// waves per SIMD the G2P backward is built for (caps its registers)
+constexpr int ADJ_WAVES_PER_EU = 2;
+
 template <int DIM, int MAT> constexpr int LROWS() { return 2 * DIM + DIM * DIM + nc3<DIM, MAT>(); }
 
 // d w / d x_a for a node with offsets o: inv_dx N'_{o_a}(f_a) prod_{b!=a} N_{o_b}(f_b)
@@ -154,18 +157,147 @@ __device__ __forceinline__ void stencil_all(const DevParams &P, const double *xd
     }
 }
 
+// lambda_t contributions that reach the node adjoints: lambda_v' and
+// lambda_C' of particle p, with the VJP of F' = (I + dt C') F (fluid:
+// J' = J (1 + dt tr C')) added to lambda_C' and that of x' = x + dt v' to
+// lambda_v'.  Also returns lambda_x' and lambda_F' as read.
+template <int DIM, int MAT>
+__device__ __forceinline__ void adj_lambda_in(const DevParams &P, const float *__restrict__ lin, int64_t n,
+                                              int64_t p, const float *F, float *lx, float *lv, float *lC,
+                                              float *lF) {
+    constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        lx[a] = lin[a * n + p];
+        lv[a] = lin[(DIM + a) * n + p];
+    }
+#pragma unroll
+    for (int c = 0; c < D2; ++c) lC[c] = lin[(2 * DIM + c) * n + p];
+#pragma unroll
+    for (int c = 0; c < N3; ++c) lF[c] = lin[(2 * DIM + D2 + c) * n + p];
+    if constexpr (MAT == 1) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) lC[a * DIM + a] += lF[0] * F[0] * P.dt;
+    } else {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                float aC = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) aC += lF[i * DIM + k] * F[j * DIM + k];
+                lC[i * DIM + j] += P.dt * aC;
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) lv[a] += P.dt * lx[a];
+}
+
+// Bound on |w (lambda_v'_a + D sum_b lambda_C'_ab d_b)| over the stencil of a
+// particle: w <= 1 and |d_b| <= 1.5 dx, so D |d_b| <= 6 / dx.
+template <int DIM>
+__device__ __forceinline__ float adj_node_bound(const DevParams &P, const float *lv, const float *lC) {
+    float bmax = 0.0f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float sc = 0.0f;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) sc += fabsf(lC[a * DIM + b]);
+        const float b = fabsf(lv[a]) + 6.0f * P.inv_dx * sc;
+        bmax = (b > bmax || b != b) ? b : bmax;  // NaN propagates
+    }
+    return bmax;
+}
+
+// Fixed-point scale of the node-adjoint tile: contributions of magnitude
+// below 2^e (e from the item's bound) map to integers below 2^46, so sums
+// over up to 2^16 particles stay below 2^62 and the magic-number rounding of
+// fixp (exact for |value| < 2^51) applies.
+constexpr int ADJ_FIX_BITS = 46;
+
+// Node adjoints of one particle's G2P: for each stencil node, lambda_v_i
+// gains w (lambda_v' + D lambda_C' d), and the particle's lambda_x gains the
+// weight-gradient and dpos terms.  TILE: node velocities come from the LDS
+// tile `gv` and the node adjoints go to the LDS tile `tacc` (both with
+// corner offset l0): as integers of scale `fs` when FIX, else as floats;
+// otherwise both go straight to the grid buffers.
+template <int DIM, bool TILE, bool FIX>
+__device__ __forceinline__ void adj_g2p_nodes(const DevParams &P, const int *base, const float *fx,
+                                              const float (*w)[3], const float (*dw)[3], const float *lv,
+                                              const float *lC, const GNode *__restrict__ grid,
+                                              const float *gv, int l0, unsigned long long *tacc, double fs,
+                                              float4 *__restrict__ nadj, float *ox) {
+    constexpr int NST = Geo<DIM>::NST, TB = Geo<DIM>::TB, TN = Geo<DIM>::TN;
+    const float D = 4.0f * P.inv_dx * P.inv_dx;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        float wt = 1.0f, d[DIM], gw[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            wt *= w[a][o[a]];
+            d[a] = ((float)o[a] - fx[a]) * P.dx;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            gw[a] = dw[a][o[a]];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b)
+                if (b != a) gw[a] *= w[b][o[b]];
+        }
+        float vi[3] = {0.0f, 0.0f, 0.0f};
+        int lt = 0;
+        float *na = nullptr;
+        if constexpr (TILE) {
+            lt = l0 + ((DIM == 3) ? (o[2] * TB + o[1]) * TB + o[0] : o[1] * TB + o[0]);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) vi[a] = gv[a * TN + lt];
+        } else {
+            int ijk[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ijk[a] = base[a] + o[a];
+            const int64_t id = node_index<DIM>(ijk, P.nb);
+            const float4 g = node_vel<DIM>(grid, id);
+            vi[0] = g.x;
+            vi[1] = g.y;
+            vi[2] = g.z;
+            na = reinterpret_cast<float *>(nadj + id);
+        }
+        float lw = 0.0f;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float ld = 0.0f;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) ld += lC[a * DIM + b] * d[b];
+            const float c = wt * (lv[a] + D * ld);
+            if constexpr (TILE && FIX) atomicAdd(&tacc[a * TN + lt], fixp((double)c, fs));
+            else if constexpr (TILE) atomicAdd(reinterpret_cast<float *>(tacc) + a * TN + lt, c);
+            else unsafeAtomicAdd(na + a, c);
+            lw += lv[a] * vi[a] + D * vi[a] * ld;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) ox[b] -= D * wt * lC[a * DIM + b] * vi[a];
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ox[a] += gw[a] * lw;
+    }
+}
+
 // G2P backward of particle p: from lambda_{t+1} (of x', v', C', F') to the
-// partial lambda_t of x and F, and the node adjoints lambda_v_i, added into
-// the LDS tile `tacc` (3 x TN floats, tile corner `origin`) when the
-// particle's stencil lies in it, else into the grid-wide `nadj` with atomics.
+// partial lambda_t of x and F, and the node adjoints lambda_v_i.  A particle
+// whose stencil lies in the item's tile (corner `origin`) reads node
+// velocities from the LDS tile `gv` and adds its node adjoints into the LDS
+// tile `tacc` (3 x TN; integers of scale `fs` when `fix`, else floats); any
+// other reads and adds the grid buffers.
 template <int DIM, int MAT>
 __device__ __forceinline__ void adj_g2p_particle(const DevScheme *__restrict__ sch, const DevParams &P,
                                                  const uint32_t *__restrict__ words, int64_t cap, int64_t n,
                                                  int64_t p, const GNode *__restrict__ grid,
                                                  const float *__restrict__ lin, float *__restrict__ lout,
-                                                 float4 *__restrict__ nadj, float *tacc, const int *origin) {
-    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST, N3 = nc3<DIM, MAT>();
-    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN;
+                                                 float4 *__restrict__ nadj, const float *gv,
+                                                 unsigned long long *tacc, bool fix, double fs,
+                                                 const int *origin) {
+    constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
+    constexpr int TB = Geo<DIM>::TB;
     SchemeRef s = scheme_ref(sch);
     const uint32_t p4 = (uint32_t)p * 4u;
     double xd[DIM];
@@ -183,108 +315,56 @@ __device__ __forceinline__ void adj_g2p_particle(const DevScheme *__restrict__ s
         in_tile &= (la >= 0) && (la <= TB - 3);
         l0 = l0 * TB + la;
     }
-    const float D = 4.0f * P.inv_dx * P.inv_dx;
-    // recompute C' for the F' adjoint
-    float Cn[D2];
+    // recompute C' for the F' adjoint, as the forward G2P forms it
+    float nv[DIM], S[DIM][DIM];
 #pragma unroll
-    for (int c = 0; c < D2; ++c) Cn[c] = 0.0f;
+    for (int a = 0; a < DIM; ++a) {
+        nv[a] = 0.0f;
 #pragma unroll
-    for (int st = 0; st < NST; ++st) {
-        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
-        int ijk[DIM];
-        float wt = 1.0f, d[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            ijk[a] = base[a] + o[a];
-            wt *= w[a][o[a]];
-            d[a] = ((float)o[a] - fx[a]) * P.dx;
-        }
-        const float4 g = node_vel<DIM>(grid, node_index<DIM>(ijk, P.nb));
-        const float vi[3] = {g.x, g.y, g.z};
+        for (int b = 0; b < DIM; ++b) S[b][a] = 0.0f;
+    }
+    if (in_tile) {
+        g2p_tile<DIM>(gv, l0, w, fx, nv, S);
+    } else {
+        float wd[DIM][3];  // w (o - f)
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
 #pragma unroll
-            for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] += D * wt * vi[a] * d[b];
+            for (int o = 0; o < 3; ++o) wd[a][o] = w[a][o] * ((float)o - fx[a]);
+        g2p_global<DIM>(grid, P.nb, base, w, wd, nv, S);
     }
+    float Cn[D2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) Cn[a * DIM + b] = 4.0f * P.inv_dx * S[b][a];
     float lx[DIM], lv[DIM], lC[D2], lF[N3], oF[N3];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        lx[a] = lin[a * n + p];
-        lv[a] = lin[(DIM + a) * n + p];
-    }
-#pragma unroll
-    for (int c = 0; c < D2; ++c) lC[c] = lin[(2 * DIM + c) * n + p];
-#pragma unroll
-    for (int c = 0; c < N3; ++c) lF[c] = lin[(2 * DIM + D2 + c) * n + p];
+    adj_lambda_in<DIM, MAT>(P, lin, n, p, F, lx, lv, lC, lF);
     if constexpr (MAT == 1) {
-        // J' = J (1 + dt tr C')
         float tr = 0.0f;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) tr += Cn[a * DIM + a];
         oF[0] = lF[0] * (1.0f + P.dt * tr);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) lC[a * DIM + a] += lF[0] * F[0] * P.dt;
     } else {
-        // F' = (I + dt C') F
 #pragma unroll
         for (int i = 0; i < DIM; ++i)
 #pragma unroll
             for (int j = 0; j < DIM; ++j) {
-                float aF = 0.0f, aC = 0.0f;
+                float aF = 0.0f;
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) {
-                    const float Mki = ((k == i) ? 1.0f : 0.0f) + P.dt * Cn[k * DIM + i];
-                    aF += Mki * lF[k * DIM + j];
-                    aC += lF[i * DIM + k] * F[j * DIM + k];
-                }
+                for (int k = 0; k < DIM; ++k)
+                    aF += (((k == i) ? 1.0f : 0.0f) + P.dt * Cn[k * DIM + i]) * lF[k * DIM + j];
                 oF[i * DIM + j] = aF;
-                lC[i * DIM + j] += P.dt * aC;
             }
     }
-    // x' = x + dt v'
     float ox[DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        ox[a] = lx[a];
-        lv[a] += P.dt * lx[a];
-    }
-#pragma unroll
-    for (int st = 0; st < NST; ++st) {
-        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
-        int ijk[DIM];
-        float wt = 1.0f, d[DIM], gw[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            ijk[a] = base[a] + o[a];
-            wt *= w[a][o[a]];
-            d[a] = ((float)o[a] - fx[a]) * P.dx;
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            gw[a] = dw[a][o[a]];
-#pragma unroll
-            for (int b = 0; b < DIM; ++b)
-                if (b != a) gw[a] *= w[b][o[b]];
-        }
-        const int64_t id = node_index<DIM>(ijk, P.nb);
-        const float4 g = node_vel<DIM>(grid, id);
-        const float vi[3] = {g.x, g.y, g.z};
-        float lw = 0.0f;
-        float *na = reinterpret_cast<float *>(nadj + id);
-        const int lt = l0 + ((DIM == 3) ? (o[2] * TB + o[1]) * TB + o[0] : o[1] * TB + o[0]);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            float ld = 0.0f;
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) ld += lC[a * DIM + b] * d[b];
-            if (in_tile) atomicAdd(&tacc[a * TN + lt], wt * (lv[a] + D * ld));
-            else unsafeAtomicAdd(na + a, wt * (lv[a] + D * ld));
-            lw += lv[a] * vi[a] + D * vi[a] * ld;
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) ox[b] -= D * wt * lC[a * DIM + b] * vi[a];
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) ox[a] += gw[a] * lw;
+    for (int a = 0; a < DIM; ++a) ox[a] = lx[a];
+    if (in_tile) {
+        if (fix) adj_g2p_nodes<DIM, true, true>(P, base, fx, w, dw, lv, lC, grid, gv, l0, tacc, fs, nadj, ox);
+        else adj_g2p_nodes<DIM, true, false>(P, base, fx, w, dw, lv, lC, grid, gv, l0, tacc, fs, nadj, ox);
+    } else {
+        adj_g2p_nodes<DIM, false, false>(P, base, fx, w, dw, lv, lC, grid, gv, l0, tacc, fs, nadj, ox);
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -297,18 +377,24 @@ __device__ __forceinline__ void adj_g2p_particle(const DevScheme *__restrict__ s
     for (int c = 0; c < N3; ++c) lout[(2 * DIM + D2 + c) * n + p] = oF[c];
 }
 
-// Per work item (the forward's sort): node adjoints of the item's particles
-// accumulate in an LDS tile, which is then added to `nadj` with one atomic
-// per non-zero node component.
+// Per work item (the forward's sort): the item's node velocities are staged
+// in an LDS tile; node adjoints of its particles accumulate in a second LDS
+// tile, as 64-bit fixed point whose scale comes from a bound over the item's
+// particles (exact, order-independent sums; LDS integer atomics are much
+// cheaper than float ones), or as floats when that bound is not finite.  The
+// tile is then added to `nadj` with one float atomic per non-zero node
+// component.
 template <int DIM, int MAT>
-__global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sch, DevParams P,
+__global__ __launch_bounds__(WG, ADJ_WAVES_PER_EU) void k_adj_g2p(const DevScheme *__restrict__ sch, DevParams P,
                                                 const uint32_t *__restrict__ words, int64_t cap, int64_t n,
                                                 const WorkItem *__restrict__ items,
                                                 const uint32_t *__restrict__ n_items,
                                                 const GNode *__restrict__ grid, const float *__restrict__ lin,
                                                 float *__restrict__ lout, float4 *__restrict__ nadj) {
-    constexpr int TN = Geo<DIM>::TN;
-    __shared__ float tacc[3 * TN];
+    constexpr int TN = Geo<DIM>::TN, D2 = DIM * DIM, N3 = nc3<DIM, MAT>();
+    __shared__ float gv[DIM * TN];
+    __shared__ unsigned long long tacc[3 * TN];
+    __shared__ uint32_t sbound;
     const uint32_t nit = *n_items;
     const ItemWalk walk(nit);
     for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
@@ -316,17 +402,54 @@ __global__ __launch_bounds__(WG) void k_adj_g2p(const DevScheme *__restrict__ sc
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
-        for (int t = threadIdx.x; t < 3 * TN; t += WG) tacc[t] = 0.0f;
+        if (threadIdx.x == 0) sbound = 0u;
+        for (int t = threadIdx.x; t < TN; t += WG) {
+            int ijk[DIM];
+            float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (tile_node<DIM>(t, origin, P.res, ijk)) g = node_vel<DIM>(grid, node_index<DIM>(ijk, P.nb));
+            gv[t] = g.x;
+            gv[TN + t] = g.y;
+            if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
+        }
+        for (int t = threadIdx.x; t < 3 * TN; t += WG) tacc[t] = 0ull;
         __syncthreads();
+        {
+            // bound of the item's node-adjoint contributions (non-negative
+            // floats order as their bit patterns; NaN and inf sort above)
+            SchemeRef s = scheme_ref(sch);
+            float bmax = 0.0f;
+            for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += WG) {
+                float F[N3], lx[DIM], lv[DIM], lC[D2], lF[N3];
+                dec_field<DIM, fid3<MAT>(), float>(&s->f[3], words, cap, (uint32_t)p * 4u, F);
+                adj_lambda_in<DIM, MAT>(P, lin, n, p, F, lx, lv, lC, lF);
+                const float b = adj_node_bound<DIM>(P, lv, lC);
+                bmax = (b > bmax || b != b) ? b : bmax;
+            }
+            atomicMax(&sbound, __float_as_uint(bmax) & 0x7fffffffu);
+        }
+        __syncthreads();
+        const uint32_t bb = sbound;
+        const bool fix = bb < 0x7f800000u;
+        int e = 0;
+        (void)frexpf(__uint_as_float(bb), &e);
+        const double fs = fix ? ldexp(1.0, ADJ_FIX_BITS - e) : 1.0;
+        const double inv_fs = fix ? ldexp(1.0, e - ADJ_FIX_BITS) : 1.0;
         for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += WG)
-            adj_g2p_particle<DIM, MAT>(sch, P, words, cap, n, p, grid, lin, lout, nadj, tacc, origin);
+            adj_g2p_particle<DIM, MAT>(sch, P, words, cap, n, p, grid, lin, lout, nadj, gv, tacc, fix, fs, origin);
         __syncthreads();
         // lanes take (node, component) pairs: adjacent lanes, adjacent words
         for (int q = threadIdx.x; q < 4 * TN; q += WG) {
             const int t = q >> 2, c = q & 3;
             if (c >= DIM) continue;
-            const float v = tacc[c * TN + t];
-            if (v == 0.0f) continue;
+            float v;
+            if (fix) {
+                const unsigned long long u = tacc[c * TN + t];
+                if (u == 0ull) continue;
+                v = (float)((double)(long long)u * inv_fs);
+            } else {
+                v = reinterpret_cast<const float *>(tacc)[c * TN + t];
+                if (v == 0.0f) continue;
+            }
             int ijk[DIM];
             if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached: stencils stay in-grid
             unsafeAtomicAdd(reinterpret_cast<float *>(nadj + node_index<DIM>(ijk, P.nb)) + c, v);
