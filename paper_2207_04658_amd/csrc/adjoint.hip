@@ -494,15 +494,72 @@ __global__ __launch_bounds__(WG) void k_adj_grid(DevParams P, const GNode *__res
     nadj[id] = make_float4(out[0], out[1], out[2], out[3]);
 }
 
-// P2G backward: gathers (lambda_mom_i, lambda_m_i) and adds the partial
-// lambda_t of x, v, C and F (stress through its VJP).
+// Gathers of one particle's P2G backward over its stencil: lambda_x,
+// lambda_v and lambda_A from the node adjoints (lambda_mom_i, lambda_m_i).
+// TILE: node adjoints come from the LDS tile `nt` (corner offset l0), else
+// from the grid-wide array.
+template <int DIM, bool TILE>
+__device__ __forceinline__ void adj_p2g_nodes(const DevParams &P, const int *base, const float *fx,
+                                              const float (*w)[3], const float (*dw)[3], const float *v,
+                                              const float *A, const float4 *__restrict__ nadj, const float4 *nt,
+                                              int l0, float *lx, float *lv, float *lA) {
+    constexpr int NST = Geo<DIM>::NST, TB = Geo<DIM>::TB;
+    const float m = P.p_mass;
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
+        float wt = 1.0f, d[DIM], gw[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            wt *= w[a][o[a]];
+            d[a] = ((float)o[a] - fx[a]) * P.dx;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            gw[a] = dw[a][o[a]];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b)
+                if (b != a) gw[a] *= w[b][o[b]];
+        }
+        float4 la;
+        if constexpr (TILE) {
+            la = nt[l0 + ((DIM == 3) ? (o[2] * TB + o[1]) * TB + o[0] : o[1] * TB + o[0])];
+        } else {
+            int ijk[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ijk[a] = base[a] + o[a];
+            la = nadj[node_index<DIM>(ijk, P.nb)];
+        }
+        const float lmo[3] = {la.x, la.y, la.z};
+        float lw = la.w * m;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            float Ad = 0.0f;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) Ad += A[a * DIM + b] * d[b];
+            lw += lmo[a] * (m * v[a] + Ad);
+            lv[a] += wt * m * lmo[a];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                lA[a * DIM + b] += wt * lmo[a] * d[b];
+                lx[b] -= wt * lmo[a] * A[a * DIM + b];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) lx[a] += gw[a] * lw;
+    }
+}
+
+// P2G backward of particle p: gathers (lambda_mom_i, lambda_m_i) and adds the
+// partial lambda_t of x, v, C and F (stress through its VJP).  A particle
+// whose stencil lies in the item's tile (corner `origin`) reads the node
+// adjoints from the LDS tile `nt`.
 template <int DIM, int MAT>
-__global__ __launch_bounds__(WG) void k_adj_p2g(const DevScheme *__restrict__ sch, DevParams P,
-                                                const uint32_t *__restrict__ words, int64_t cap, int64_t n,
-                                                const float4 *__restrict__ nadj, float *__restrict__ lout) {
-    constexpr int D2 = DIM * DIM, NST = Geo<DIM>::NST, N3 = nc3<DIM, MAT>();
-    const int64_t p = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (p >= n) return;
+__device__ __forceinline__ void adj_p2g_particle(const DevScheme *__restrict__ sch, const DevParams &P,
+                                                 const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                 int64_t p, const float4 *__restrict__ nadj, const float4 *nt,
+                                                 const int *origin, float *__restrict__ lout) {
+    constexpr int D2 = DIM * DIM, N3 = nc3<DIM, MAT>(), TB = Geo<DIM>::TB;
     SchemeRef s = scheme_ref(sch);
     const uint32_t p4 = (uint32_t)p * 4u;
     double xd[DIM];
@@ -542,43 +599,17 @@ __global__ __launch_bounds__(WG) void k_adj_p2g(const DevScheme *__restrict__ sc
     for (int a = 0; a < DIM; ++a) lx[a] = lv[a] = 0.0f;
 #pragma unroll
     for (int c = 0; c < D2; ++c) lA[c] = 0.0f;
+    bool in_tile = true;
+    int l0 = 0;
 #pragma unroll
-    for (int st = 0; st < NST; ++st) {
-        const int o[3] = {st % 3, (st / 3) % 3, st / 9};
-        int ijk[DIM];
-        float wt = 1.0f, d[DIM], gw[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            ijk[a] = base[a] + o[a];
-            wt *= w[a][o[a]];
-            d[a] = ((float)o[a] - fx[a]) * P.dx;
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            gw[a] = dw[a][o[a]];
-#pragma unroll
-            for (int b = 0; b < DIM; ++b)
-                if (b != a) gw[a] *= w[b][o[b]];
-        }
-        const float4 la = nadj[node_index<DIM>(ijk, P.nb)];
-        const float lmo[3] = {la.x, la.y, la.z};
-        float lw = la.w * m;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            float Ad = 0.0f;
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) Ad += A[a * DIM + b] * d[b];
-            lw += lmo[a] * (m * v[a] + Ad);
-            lv[a] += wt * m * lmo[a];
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) {
-                lA[a * DIM + b] += wt * lmo[a] * d[b];
-                lx[b] -= wt * lmo[a] * A[a * DIM + b];
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) lx[a] += gw[a] * lw;
+    for (int a = DIM - 1; a >= 0; --a) {
+        const int la = base[a] - origin[a];
+        in_tile &= (la >= 0) && (la <= TB - 3);
+        l0 = l0 * TB + la;
     }
+    if (in_tile) adj_p2g_nodes<DIM, true>(P, base, fx, w, dw, v, A, nadj, nt, l0, lx, lv, lA);
+    else adj_p2g_nodes<DIM, false>(P, base, fx, w, dw, v, A, nadj, nt, l0, lx, lv, lA);
+
     // A = p_mass stress_over_m tau + p_mass C
     float lt[D2], lF[N3];
 #pragma unroll
@@ -602,6 +633,35 @@ __global__ __launch_bounds__(WG) void k_adj_p2g(const DevScheme *__restrict__ sc
     for (int c = 0; c < D2; ++c) lout[(2 * DIM + c) * n + p] += m * lA[c];
 #pragma unroll
     for (int c = 0; c < N3; ++c) lout[(2 * DIM + D2 + c) * n + p] += lF[c];
+}
+
+// Per work item: the node adjoints of the item's tile are staged in LDS
+// (zero outside the grid), then each particle gathers from them.
+template <int DIM, int MAT>
+__global__ __launch_bounds__(WG, ADJ_WAVES_PER_EU) void k_adj_p2g(const DevScheme *__restrict__ sch, DevParams P,
+                                                const uint32_t *__restrict__ words, int64_t cap, int64_t n,
+                                                const WorkItem *__restrict__ items,
+                                                const uint32_t *__restrict__ n_items,
+                                                const float4 *__restrict__ nadj, float *__restrict__ lout) {
+    constexpr int TN = Geo<DIM>::TN;
+    __shared__ float4 nt[TN];
+    const uint32_t nit = *n_items;
+    const ItemWalk walk(nit);
+    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
+        const WorkItem it = items[item];
+        int origin[DIM];
+        tile_origin<DIM>(it.block, P.nb, origin);
+        __syncthreads();
+        for (int t = threadIdx.x; t < TN; t += WG) {
+            int ijk[DIM];
+            float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (tile_node<DIM>(t, origin, P.res, ijk)) g = nadj[node_index<DIM>(ijk, P.nb)];
+            nt[t] = g;
+        }
+        __syncthreads();
+        for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += WG)
+            adj_p2g_particle<DIM, MAT>(sch, P, words, cap, n, p, nadj, nt, origin, lout);
+    }
 }
 
 // Objective at the final state: 0 = centre of mass along `axis`, 1 = kinetic
@@ -796,7 +856,7 @@ hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams
                       nadj);
     if (dim == 3) hipLaunchKernelGGL(k_adj_grid<3>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
     else hipLaunchKernelGGL(k_adj_grid<2>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
-    MPMQ_ADJ_DISPATCH(k_adj_p2g, agrid(n), s, P, words, cap, n, nadj, lout);
+    MPMQ_ADJ_DISPATCH(k_adj_p2g, dim3((unsigned)item_grid), s, P, words, cap, n, items, n_items, nadj, lout);
     return hipGetLastError();
 }
 
