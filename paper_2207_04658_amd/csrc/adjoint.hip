@@ -635,19 +635,24 @@ __device__ __forceinline__ void adj_p2g_particle(const DevScheme *__restrict__ s
     for (int c = 0; c < N3; ++c) lout[(2 * DIM + D2 + c) * n + p] += lF[c];
 }
 
-// Per work item: the node adjoints of the item's tile are staged in LDS
-// (zero outside the grid), then each particle gathers from them.
+// Per slice of a work item (`slices` per item, slice k taking the item's
+// particles k WG, (k + slices) WG, ...; groups of different slices of one item
+// load the same tile): the node adjoints of the item's tile are staged in
+// LDS (zero outside the grid), then each particle gathers from them.  The
+// gather has no accumulation tile to flush, so it splits items into
+// work-group-sized slices: more groups in flight on small scenes.
 template <int DIM, int MAT>
 __global__ __launch_bounds__(WG, ADJ_WAVES_PER_EU) void k_adj_p2g(const DevScheme *__restrict__ sch, DevParams P,
                                                 const uint32_t *__restrict__ words, int64_t cap, int64_t n,
                                                 const WorkItem *__restrict__ items,
-                                                const uint32_t *__restrict__ n_items,
+                                                const uint32_t *__restrict__ n_items, int slices,
                                                 const float4 *__restrict__ nadj, float *__restrict__ lout) {
     constexpr int TN = Geo<DIM>::TN;
     __shared__ float4 nt[TN];
     const uint32_t nit = *n_items;
-    const ItemWalk walk(nit);
-    for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
+    const ItemWalk walk(nit * (uint32_t)slices);
+    for (uint32_t vit = walk.first; vit < walk.end; vit += walk.stride) {
+        const uint32_t item = vit / (uint32_t)slices, slice = vit % (uint32_t)slices;
         const WorkItem it = items[item];
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
@@ -659,7 +664,7 @@ __global__ __launch_bounds__(WG, ADJ_WAVES_PER_EU) void k_adj_p2g(const DevSchem
             nt[t] = g;
         }
         __syncthreads();
-        for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += WG)
+        for (int64_t p = it.p0 + (int64_t)slice * WG + threadIdx.x; p < it.p1; p += (int64_t)slices * WG)
             adj_p2g_particle<DIM, MAT>(sch, P, words, cap, n, p, nadj, nt, origin, lout);
     }
 }
@@ -848,6 +853,7 @@ hipError_t launch_adj_objective(int dim, int mat, const DevScheme *s, const DevP
 
 hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words,
                            int64_t cap, int64_t n, const WorkItem *items, const uint32_t *n_items, int item_grid,
+                           int item_cap,
                            const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
                            hipStream_t st) {
     hipLaunchKernelGGL(k_zero_f4, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 65536)), dim3(256), 0, st,
@@ -856,7 +862,11 @@ hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams
                       nadj);
     if (dim == 3) hipLaunchKernelGGL(k_adj_grid<3>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
     else hipLaunchKernelGGL(k_adj_grid<2>, agrid(nodes), dim3(WG), 0, st, P, grid, nadj, nodes);
-    MPMQ_ADJ_DISPATCH(k_adj_p2g, dim3((unsigned)item_grid), s, P, words, cap, n, items, n_items, nadj, lout);
+    // one group per work-group pass of an item (a multiple of the 8 XCDs)
+    const int slices = std::max(1, item_cap / WG);
+    const int p2g_grid = (int)std::min<int64_t>((int64_t)item_grid * slices, 131072);
+    MPMQ_ADJ_DISPATCH(k_adj_p2g, dim3((unsigned)p2g_grid), s, P, words, cap, n, items, n_items, slices, nadj,
+                      lout);
     return hipGetLastError();
 }
 

@@ -154,10 +154,11 @@ hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams 
 // g[4]; rng: uint32 order keys min[4], max[4].
 hipError_t launch_adj_objective(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
                                 int64_t n, int objective, int axis, float *lam, double *acc, hipStream_t st);
-// items / n_items / item_grid: the work items of the last sort (the adjoint's
-// G2P backward accumulates node adjoints per item tile)
+// items / n_items / item_grid / item_cap: the work items of the last sort and
+// their particle limit (the adjoint's G2P backward accumulates node adjoints
+// per item tile; its P2G backward gathers them from per-item tiles)
 hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams &P, const uint32_t *words, int64_t cap,
-                           int64_t n, const WorkItem *items, const uint32_t *n_items, int item_grid,
+                           int64_t n, const WorkItem *items, const uint32_t *n_items, int item_grid, int item_cap,
                            const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
                            hipStream_t st);
 hipError_t launch_adj_reduce(int dim, int mat, const float *lam, int64_t n, double *acc, hipStream_t st);

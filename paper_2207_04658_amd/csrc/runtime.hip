@@ -501,7 +501,7 @@ struct AdjRun {
         {
             Timed tm(c, "adjoint_step");
             HIPCHK(c, launch_adj_step(c->dim, c->ds.mat, c->dscheme(), c->dp, words, c->cap_pad, c->n, c->items(),
-                                      c->n_items(), c->launch_grid, c->grid[0], w.nodes,
+                                      c->n_items(), c->launch_grid, c->item_cap, c->grid[0], w.nodes,
                                       lam_cur, lam_nxt, nadj(), st), "adjoint: step");
         }
         HIPCHK(c, launch_adj_reduce(c->dim, c->ds.mat, lam_nxt, c->n, acc(), st), "adjoint: reduce");
