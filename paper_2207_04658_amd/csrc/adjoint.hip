@@ -742,7 +742,8 @@ __global__ __launch_bounds__(WG) void k_adj_reduce(const float *__restrict__ lam
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < WG / 64; ++w) t += part[w][threadIdx.x];
-        atomicAdd(acc + 1 + threadIdx.x, t);  // acc[1..4]: sums, acc[5..8]: sums of squares
+        // copy b % ADJ_SLOTS of the sums (k < 4) and sums of squares (k >= 4)
+        atomicAdd(acc + 1 + 8 * (blockIdx.x % ADJ_SLOTS) + threadIdx.x, t);
     }
 }
 
@@ -816,8 +817,9 @@ __global__ __launch_bounds__(WG) void k_adj_range(const DevScheme *__restrict__ 
         uint32_t t = part[0][threadIdx.x];
 #pragma unroll
         for (int w = 1; w < WG / 64; ++w) t = (threadIdx.x < 4) ? min(t, part[w][threadIdx.x]) : max(t, part[w][threadIdx.x]);
-        if (threadIdx.x < 4) atomicMin(rng + threadIdx.x, t);
-        else atomicMax(rng + threadIdx.x, t);  // rng[4..7]: maxima
+        const uint32_t slot = 4u * (blockIdx.x % ADJ_SLOTS);
+        if (threadIdx.x < 4) atomicMin(rng + slot + threadIdx.x, t);
+        else atomicMax(rng + 4 * ADJ_SLOTS + slot + (threadIdx.x - 4), t);
     }
 }
 
@@ -833,8 +835,9 @@ __global__ void k_adj_unpermute(const float *__restrict__ lam, const uint32_t *_
 }
 
 static dim3 agrid(int64_t n) { return dim3((unsigned)((n + WG - 1) / WG)); }
-// reductions: at most 256 groups (grid-stride), one atomic per group and sum
-static dim3 rgrid(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + WG - 1) / WG, 256)); }
+// reductions: at most 1024 groups (grid-stride), one atomic per group and
+// sum, into ADJ_SLOTS copies
+static dim3 rgrid(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + WG - 1) / WG, 1024)); }
 
 #define MPMQ_ADJ_DISPATCH(KERNEL, GRID, ...)                                                              \
     do {                                                                                                 \

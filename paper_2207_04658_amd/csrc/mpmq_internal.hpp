@@ -161,7 +161,17 @@ hipError_t launch_adj_step(int dim, int mat, const DevScheme *s, const DevParams
                            int64_t n, const WorkItem *items, const uint32_t *n_items, int item_grid, int item_cap,
                            const GNode *grid, int64_t nodes, const float *lin, float *lout, float4 *nadj,
                            hipStream_t st);
+// The adjoint's per-field reductions add into ADJ_SLOTS copies of their
+// accumulators (work-group b into copy b % ADJ_SLOTS; the host combines
+// them): device-wide atomics on one address serialize, and a few hundred
+// groups on one copy cost more than the reduction itself.
+constexpr int ADJ_SLOTS = 64;
+// acc[0]: objective z; acc[1 + 8 s + k]: copy s of the sums of lambda
+// (k = field) and of lambda^2 (k = 4 + field).
+constexpr int ADJ_ACC_DOUBLES = 1 + 8 * ADJ_SLOTS;
 hipError_t launch_adj_reduce(int dim, int mat, const float *lam, int64_t n, double *acc, hipStream_t st);
+// rng[4 s + f]: copy s of the minimum key of field f; rng[4 ADJ_SLOTS + 4 s + f]:
+// of its maximum key
 hipError_t launch_adj_range(int dim, int mat, const DevScheme *s, const uint32_t *words, int64_t cap, int64_t n, uint32_t *rng,
                             hipStream_t st);
 hipError_t launch_adj_unpermute(const float *lam, const uint32_t *ids, int64_t n, int rows, float *out,

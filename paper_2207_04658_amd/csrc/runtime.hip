@@ -423,7 +423,7 @@ AdjWork adj_layout(const mpmq_ctx *c, const AdjPlan &plan) {
     w.off_final = o; o += w.state_bytes;
     w.off_lam = o; o += 2 * w.lam_bytes;
     w.off_nadj = o; o = align256(o + 16 * w.nodes);
-    w.off_acc = o; o = align256(o + 8 * 16 + 4 * 8);
+    w.off_acc = o; o = align256(o + 8 * ADJ_ACC_DOUBLES + 4 * 8 * ADJ_SLOTS);
     w.off_stats = o; o = align256(o + 8 * ST_COUNT);
     w.total = o;
     return w;
@@ -453,7 +453,7 @@ struct AdjRun {
     uint32_t *slot_ptr(int s) { return reinterpret_cast<uint32_t *>(ws + w.off_states + (int64_t)s * w.state_bytes); }
     uint32_t *final_ptr() { return reinterpret_cast<uint32_t *>(ws + w.off_final); }
     double *acc() { return reinterpret_cast<double *>(ws + w.off_acc); }
-    uint32_t *rng() { return reinterpret_cast<uint32_t *>(ws + w.off_acc + 8 * 16); }
+    uint32_t *rng() { return reinterpret_cast<uint32_t *>(ws + w.off_acc + 8 * ADJ_ACC_DOUBLES); }
     float4 *nadj() { return reinterpret_cast<float4 *>(ws + w.off_nadj); }
     int64_t state_words() const { return (int64_t)c->W * c->cap_pad; }
 
@@ -813,9 +813,9 @@ mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
     run.lam_cur = reinterpret_cast<float *>(run.ws + run.w.off_lam);
     run.lam_nxt = reinterpret_cast<float *>(run.ws + run.w.off_lam + run.w.lam_bytes);
     for (int s = (int)plan.slots - 1; s >= 0; --s) run.free_slots.push_back(s);
-    HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(run.acc()), 0u, 2 * 16, st), "adjoint: clear");
-    HIPCHK(c, launch_fill_u32(run.rng(), 0xffffffffu, 4, st), "adjoint: clear");
-    HIPCHK(c, launch_fill_u32(run.rng() + 4, 0u, 4, st), "adjoint: clear");
+    HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(run.acc()), 0u, 2 * ADJ_ACC_DOUBLES, st), "adjoint: clear");
+    HIPCHK(c, launch_fill_u32(run.rng(), 0xffffffffu, 4 * ADJ_SLOTS, st), "adjoint: clear");
+    HIPCHK(c, launch_fill_u32(run.rng() + 4 * ADJ_SLOTS, 0u, 4 * ADJ_SLOTS, st), "adjoint: clear");
     // forward: sort once if pending, then T substeps without re-sorting
     if (!c->sorted) {
         if (c->p2g_ready) {
@@ -880,23 +880,34 @@ mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
                               2 * ST_COUNT, st), "adjoint: stats");
     c->step = run.step0 + T;
     c->steps_taken = steps_after;
-    double acc[16];
-    uint32_t rng[8];
-    HIPCHK(c, hipMemcpyAsync(acc, run.acc(), sizeof(acc), hipMemcpyDeviceToHost, st), "adjoint: result");
-    HIPCHK(c, hipMemcpyAsync(rng, run.rng(), sizeof(rng), hipMemcpyDeviceToHost, st), "adjoint: result");
+    std::vector<double> acc(ADJ_ACC_DOUBLES);
+    std::vector<uint32_t> rng(8 * ADJ_SLOTS);
+    HIPCHK(c, hipMemcpyAsync(acc.data(), run.acc(), sizeof(double) * acc.size(), hipMemcpyDeviceToHost, st),
+           "adjoint: result");
+    HIPCHK(c, hipMemcpyAsync(rng.data(), run.rng(), sizeof(uint32_t) * rng.size(), hipMemcpyDeviceToHost, st),
+           "adjoint: result");
     HIPCHK(c, hipStreamSynchronize(st), "adjoint: sync");
     out->z = acc[0];
     for (int f = 0; f < 4; ++f) {
-        out->G[f] = acc[1 + f];
-        out->g[f] = acc[5 + f];
+        // combine the ADJ_SLOTS copies, in slot order
+        double G = 0.0, g = 0.0;
+        uint32_t klo = 0xffffffffu, khi = 0u;
+        for (int sl = 0; sl < ADJ_SLOTS; ++sl) {
+            G += acc[1 + 8 * sl + f];
+            g += acc[1 + 8 * sl + 4 + f];
+            klo = std::min(klo, rng[4 * sl + f]);
+            khi = std::max(khi, rng[4 * ADJ_SLOTS + 4 * sl + f]);
+        }
         auto unkey = [](uint32_t k) {
             const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
             float v;
             std::memcpy(&v, &u, 4);
             return (double)v;
         };
-        out->lo[f] = unkey(rng[f]);
-        out->hi[f] = unkey(rng[4 + f]);
+        out->G[f] = G;
+        out->g[f] = g;
+        out->lo[f] = unkey(klo);
+        out->hi[f] = unkey(khi);
     }
     out->recomputed = run.recomputed;
     out->states = run.max_live + 1;
