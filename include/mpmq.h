@@ -143,6 +143,9 @@ typedef struct {
     int64_t sorts;     /* particle sorts performed */
     int64_t fallback;  /* particle-stencils that left their tile (global atomics) */
     int64_t active_nodes; /* sum over substeps of grid nodes with mass > 0 */
+    int64_t clamped;   /* particle scatters (P2G) with a velocity term v - (A/m) f dx or
+                          (A/m) dx above 2^12 in magnitude, clamped so that the 64-bit
+                          fixed-point node sums cannot overflow (the clamp loses momentum) */
 } mpmq_stats_t;
 
 typedef struct mpmq_ctx mpmq_ctx;
@@ -305,6 +308,33 @@ typedef struct {
     double total_bits;     /* sum P_h bits_h */
 } mpmq_solve_output;
 mpmq_status mpmq_solve_scheme(const mpmq_solve_input *in, mpmq_solve_output *out);
+
+/* Alg. 1 from the record of a full-precision run: the per-field value
+ * ranges, the accumulated squared gradients and the objective that
+ * mpmq_adjoint returned (adj->lo, hi, g, z) become a fixed-point scheme.
+ * Per field h (state slot order x, v, C, then F or J): the recorded range
+ * [lo_h, hi_h] is widened about its centre by range_factor against
+ * overflow (Sec. 3.2 uses 2; a half-width below 2^-20 max(1, |centre|) is
+ * raised to it, so that a constant field gets a usable range),
+ * R_h = its width, P_h = n_particles x the field's component count, and the
+ * widths come from mpmq_solve_scheme with (mode, eps, z = adj->z, min_bits,
+ * max_bits).  out_fields (host, 4 entries) receives the scheme in the
+ * placement order of `base`: kind MPMQ_FIXED, the solved bits, the widened
+ * [lo, hi), and the dither flag and REL_IDENTITY flag of the matching base
+ * field (a REL_IDENTITY field's recorded range is already that of F - I).
+ * solved (optional; its arrays hold 4 entries in slot order) receives the
+ * solver's output.  Host only.  EINVAL on a NULL or invalid argument (the
+ * reason: mpmq_solver_error()). */
+typedef struct {
+    int32_t mode;          /* MPMQ_SOLVE_ERROR_BOUND or MPMQ_SOLVE_MEMORY_BOUND */
+    int32_t min_bits, max_bits;
+    int32_t reserved;      /* 0 */
+    double eps;            /* as in mpmq_solve_input */
+    double range_factor;   /* >= 1 */
+    int64_t n_particles;   /* >= 1 */
+} mpmq_auto_input;
+mpmq_status mpmq_auto_scheme(const mpmq_scheme *base, const mpmq_adjoint_result *adj, const mpmq_auto_input *in,
+                             mpmq_field_scheme *out_fields, mpmq_solve_output *solved);
 const char *mpmq_solver_error(void);
 
 const char *mpmq_error_string(mpmq_status status);

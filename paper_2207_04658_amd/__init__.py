@@ -73,7 +73,7 @@ class mpmq_buffers(ct.Structure):
 class mpmq_stats_t(ct.Structure):
     _fields_ = [("sat", ct.c_int64 * 4), ("nan", ct.c_int64 * 4), ("up", ct.c_int64 * 4),
                 ("down", ct.c_int64 * 4), ("steps", ct.c_int64), ("sorts", ct.c_int64),
-                ("fallback", ct.c_int64), ("active_nodes", ct.c_int64)]
+                ("fallback", ct.c_int64), ("active_nodes", ct.c_int64), ("clamped", ct.c_int64)]
 
 
 class mpmq_kernel_time(ct.Structure):
@@ -104,6 +104,11 @@ class mpmq_solve_input(ct.Structure):
 class mpmq_solve_output(ct.Structure):
     _fields_ = [("delta", ct.POINTER(ct.c_double)), ("b_cont", ct.POINTER(ct.c_double)),
                 ("bits", ct.POINTER(ct.c_int32)), ("expected_error", ct.c_double), ("total_bits", ct.c_double)]
+
+
+class mpmq_auto_input(ct.Structure):
+    _fields_ = [("mode", ct.c_int32), ("min_bits", ct.c_int32), ("max_bits", ct.c_int32), ("reserved", ct.c_int32),
+                ("eps", ct.c_double), ("range_factor", ct.c_double), ("n_particles", ct.c_int64)]
 
 
 _lib = None
@@ -139,6 +144,8 @@ def load(path: str = LIB_PATH):
         "mpmq_adjoint_workspace": [P, ct.POINTER(mpmq_adjoint_spec), ct.POINTER(ct.c_int64)],
         "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, ct.c_int64, P, ct.POINTER(mpmq_adjoint_result)],
         "mpmq_solve_scheme": [ct.POINTER(mpmq_solve_input), ct.POINTER(mpmq_solve_output)],
+        "mpmq_auto_scheme": [ct.POINTER(mpmq_scheme), ct.POINTER(mpmq_adjoint_result), ct.POINTER(mpmq_auto_input),
+                             ct.POINTER(mpmq_field_scheme), ct.POINTER(mpmq_solve_output)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -158,7 +165,7 @@ def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
             "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
             "mpmq_specialize",
-            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_solve_scheme", "mpmq_solver_error", "mpmq_error_string",
+            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_solve_scheme", "mpmq_auto_scheme", "mpmq_solver_error", "mpmq_error_string",
             "mpmq_last_error"]
 
 
@@ -310,7 +317,8 @@ class Context:
         names = ["x", "v", "C", self.f3]
         out = {names[i]: {"sat": st.sat[i], "nan": st.nan[i], "up": st.up[i], "down": st.down[i]}
                for i in range(4)}
-        out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes)
+        out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes,
+                   clamped=st.clamped)
         return out
 
     def set_stats(self, level):
@@ -398,30 +406,34 @@ def solve_scheme(P, g, R, mode="error", eps=1e-3, z=1.0, min_bits=1, max_bits=32
 
 def auto_scheme(base: dict, adjoint_result: dict, n: int, mode="error", eps=1e-3, range_factor=2.0,
                 min_bits=1, max_bits=32):
-    """Alg. 1: a fixed-point scheme from an adjoint run (normally of the
-    full-precision layout): per field, the recorded value range widened by
-    `range_factor` about its centre, and the bits of mpmq_solve_scheme.
-    Placement order, dither, REL_IDENTITY and the seed follow `base`."""
-    dim = base["dim"]
+    """Alg. 1 through mpmq_auto_scheme: a fixed-point scheme from an adjoint
+    run (normally of the full-precision layout): per field, the recorded
+    value range widened by `range_factor` about its centre, and the bits of
+    the closed-form solver.  Placement order, dither, REL_IDENTITY and the
+    seed follow `base`.  Returns (scheme dict, solver output dict)."""
     names = ["x", "v", "C", slot3_name(base)]
-    ncomp = {"x": dim, "v": dim, "C": dim * dim, "F": dim * dim, "J": 1}
-    lo, hi = {}, {}
-    for f in names:
-        mid = 0.5 * (adjoint_result["lo"][f] + adjoint_result["hi"][f])
-        half = 0.5 * (adjoint_result["hi"][f] - adjoint_result["lo"][f]) * range_factor
-        half = max(half, 1e-30)
-        lo[f], hi[f] = mid - half, mid + half
-    P = [float(n * ncomp[f]) for f in names]
-    g = [adjoint_result["g"][f] for f in names]
-    R = [hi[f] - lo[f] for f in names]
-    sol = solve_scheme(P, g, R, mode=mode, eps=eps, z=adjoint_result["z"], min_bits=min_bits, max_bits=max_bits)
-    fields = []
-    for fs in base["fields"]:
-        i = names.index(fs["field"])
-        fields.append({"field": fs["field"], "kind": "fixed", "bits": sol["bits"][i], "lo": lo[fs["field"]],
-                       "hi": hi[fs["field"]], "dither": fs.get("dither", False),
-                       "rel_identity": fs.get("rel_identity", False), "exp_bits": 0})
-    return {"dim": dim, "seed": base.get("seed", 0), "fields": fields}, sol
+    res = mpmq_adjoint_result()
+    res.z = float(adjoint_result["z"])
+    for i, f in enumerate(names):
+        res.g[i] = float(adjoint_result["g"][f])
+        res.lo[i] = float(adjoint_result["lo"][f])
+        res.hi[i] = float(adjoint_result["hi"][f])
+    s, keep = make_scheme(base)
+    inp = mpmq_auto_input(SOLVE_MODES[mode], int(min_bits), int(max_bits), 0, float(eps), float(range_factor), int(n))
+    out_fields = (mpmq_field_scheme * 4)()
+    arr = ct.c_double * 4
+    d, b, bits = arr(), arr(), (ct.c_int32 * 4)()
+    sol = mpmq_solve_output(d, b, bits, 0.0, 0.0)
+    st = load().mpmq_auto_scheme(ct.byref(s), ct.byref(res), ct.byref(inp), out_fields, ct.byref(sol))
+    if st != 0:
+        raise MpmqError(st, load().mpmq_solver_error().decode())
+    inv = {v: k for k, v in FIELDS.items()}
+    fields = [{"field": inv[f.field], "kind": "fixed", "bits": f.bits, "lo": f.lo, "hi": f.hi,
+               "dither": bool(f.dither), "rel_identity": bool(f.flags & REL_IDENTITY), "exp_bits": 0}
+              for f in out_fields]
+    return ({"dim": base["dim"], "seed": base.get("seed", 0), "fields": fields},
+            {"delta": list(d), "b_cont": list(b), "bits": list(bits), "expected_error": sol.expected_error,
+             "total_bits": sol.total_bits})
 
 
 class QuantizedRollout:

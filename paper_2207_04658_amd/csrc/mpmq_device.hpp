@@ -482,9 +482,142 @@ __device__ __forceinline__ void polar2(const float *F, float *R) {
     R[0] = c; R[1] = -s; R[2] = s; R[3] = c;
 }
 
-__device__ __forceinline__ void polar3(const float *F, float *R) {
+// One Jacobi rotation in the (P, Q) plane of the symmetric 3x3 matrix A
+// (row-major, indices compile-time constants so the arrays stay in
+// registers): A <- J^T A J zeroes A[P][Q]; V <- V J accumulates the
+// eigenvectors as columns.
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_rot3(float *A, float *V) {
+    const float apq = A[P * 3 + Q];
+    if (apq == 0.0f) return;
+    const float theta = (A[Q * 3 + Q] - A[P * 3 + P]) / (2.0f * apq);
+    const float t = (theta >= 0.0f ? 1.0f : -1.0f) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
+    const float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = F[i];
+    for (int k = 0; k < 3; ++k) {
+        const float akp = A[k * 3 + P], akq = A[k * 3 + Q];
+        A[k * 3 + P] = c * akp - s * akq;
+        A[k * 3 + Q] = s * akp + c * akq;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float apk = A[P * 3 + k], aqk = A[Q * 3 + k];
+        A[P * 3 + k] = c * apk - s * aqk;
+        A[Q * 3 + k] = s * apk + c * aqk;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float vkp = V[k * 3 + P], vkq = V[k * 3 + Q];
+        V[k * 3 + P] = c * vkp - s * vkq;
+        V[k * 3 + Q] = s * vkp + c * vkq;
+    }
+}
+
+__device__ __forceinline__ void cross3f(const float *a, const float *b, float *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ void normalize3f(float *a) {
+    const float n2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+    if (n2 > 0.0f) {
+        const float r = 1.0f / sqrtf(n2);
+        a[0] *= r; a[1] *= r; a[2] *= r;
+    }
+}
+
+// Closest rotation to F from its singular value decomposition, for F that
+// is inverted or nearly singular (there Newton's iteration below either
+// converges to a reflection or not at all).  F^T F = V diag(sigma^2) V^T by
+// cyclic Jacobi sweeps; the singular directions are ordered by decreasing
+// sigma and V made a proper rotation; u_a = F v_a / sigma_a for the two
+// largest (Gram-Schmidt), u_3 = u_1 x u_2; R = U V^T.  R is then the
+// fixed-corotated model's rotation: det R = +1, with the reflection of an
+// inverted F carried by the direction of its smallest singular value.
+__device__ __forceinline__ void polar3_svd(const float *F, float *R) {
+    float A[9], V[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[i * 3 + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        const float off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+        const float diag = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+        if (!(off > 1e-14f * diag)) break;
+        jacobi_rot3<0, 1>(A, V);
+        jacobi_rot3<0, 2>(A, V);
+        jacobi_rot3<1, 2>(A, V);
+    }
+    // eigenvalues with their eigenvector columns, sorted by decreasing value
+    float lam[3] = {A[0], A[4], A[8]};
+    float v[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[a][k] = V[k * 3 + a];
+    auto order = [&](int a, int b) {
+        // a < b are compile-time constants after unrolling
+        if (lam[b] > lam[a]) {
+            const float t = lam[a]; lam[a] = lam[b]; lam[b] = t;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) { const float u = v[a][k]; v[a][k] = v[b][k]; v[b][k] = u; }
+        }
+    };
+    order(0, 1);
+    order(0, 2);
+    order(1, 2);
+    float vc[3];
+    cross3f(v[0], v[1], vc);
+    if (vc[0] * v[2][0] + vc[1] * v[2][1] + vc[2] * v[2][2] < 0.0f)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[2][k] = -v[2][k];
+    const float s0 = sqrtf(fmaxf(lam[0], 0.0f)), s1 = sqrtf(fmaxf(lam[1], 0.0f));
+    if (!(s0 > 0.0f)) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+        return;
+    }
+    float u[3][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) u[a][k] = F[k * 3] * v[a][0] + F[k * 3 + 1] * v[a][1] + F[k * 3 + 2] * v[a][2];
+    normalize3f(u[0]);
+    const float d = u[1][0] * u[0][0] + u[1][1] * u[0][1] + u[1][2] * u[0][2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[1][k] -= d * u[0][k];
+    const float n1 = sqrtf(u[1][0] * u[1][0] + u[1][1] * u[1][1] + u[1][2] * u[1][2]);
+    if (!(s1 > 1e-30f) || !(n1 > 1e-5f * s0)) {
+        // rank one: any unit vector orthogonal to u_1 (from the axis least aligned with it)
+        const float ax = fabsf(u[0][0]), ay = fabsf(u[0][1]), az = fabsf(u[0][2]);
+        float e[3] = {0.0f, 0.0f, 0.0f};
+        if (ax <= ay && ax <= az) e[0] = 1.0f;
+        else if (ay <= az) e[1] = 1.0f;
+        else e[2] = 1.0f;
+        cross3f(u[0], e, u[1]);
+    }
+    normalize3f(u[1]);
+    cross3f(u[0], u[1], u[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) R[i * 3 + j] = u[0][i] * v[0][j] + u[1][i] * v[1][j] + u[2][i] * v[2][j];
+}
+
+__device__ __forceinline__ void polar3(const float *F, float *R) {
+    // Newton's iteration keeps the sign of det F: it is used where F is
+    // well inside the proper rotations' side (det F above 1e-3 of the
+    // determinant of a rotation of the same size); the other lanes -- an
+    // inverted, flattened or zero F -- take the SVD above (a rare branch)
+    const float n2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2] + F[3] * F[3] + F[4] * F[4] + F[5] * F[5] +
+                     F[6] * F[6] + F[7] * F[7] + F[8] * F[8];
+    const float detF = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                       F[2] * (F[3] * F[7] - F[4] * F[6]);
+    const float s3 = n2 * (1.0f / 3.0f);
+    const bool svd = detF <= 1e-3f * s3 * sqrtf(s3);  // NaN F: false (Newton, NaN out)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = svd ? ((i % 4 == 0) ? 1.0f : 0.0f) : F[i];
     for (int it = 0; it < 16; ++it) {
         // cofactor matrix = det * R^-T
         const float c00 = R[4] * R[8] - R[5] * R[7], c01 = R[5] * R[6] - R[3] * R[8],
@@ -512,6 +645,7 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
         // the step is under 1e-4, below float precision
         if (!__any(d2 > 1e-8f)) break;
     }
+    if (svd) polar3_svd(F, R);
 }
 
 }  // namespace mpmq

@@ -77,10 +77,11 @@ struct DevParams {
     double dt_d, inv_dx_d;
 };
 
-// Statistics slots (uint64) in scratch.
+// Statistics slots (uint64) in scratch.  ST_CLAMP: particles whose P2G
+// terms were clamped to the fixed-point range (see p2g_particle).
 enum {
     ST_SAT = 0, ST_NAN = 4, ST_UP = 8, ST_DOWN = 12, ST_FALLBACK = 16, ST_ACTIVE = 17, ST_ACTIVE_SLOTS = 7,
-    ST_COUNT = 24
+    ST_CLAMP = 24, ST_COUNT = 25
 };
 
 // Device scratch layout (byte offsets, all 256-aligned).

@@ -710,6 +710,7 @@ mpmq_status mpmq_stats(mpmq_ctx *c, mpmq_stats_t *out) {
     out->steps = c->steps_taken;
     out->sorts = c->sorts;
     out->fallback = (int64_t)h[ST_FALLBACK];
+    out->clamped = (int64_t)h[ST_CLAMP];
     out->active_nodes = 0;
     for (int i = 0; i < ST_ACTIVE_SLOTS; ++i) out->active_nodes += (int64_t)h[ST_ACTIVE + i];
     return MPMQ_OK;
@@ -786,7 +787,11 @@ mpmq_status mpmq_adjoint_workspace(mpmq_ctx *c, const mpmq_adjoint_spec *spec, i
     return MPMQ_OK;
 }
 
-mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
+}  // extern "C"
+
+namespace {
+
+mpmq_status adjoint_impl(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
                          float *lambda0, mpmq_adjoint_result *out) {
     if (!c || !out) return fail(c, MPMQ_EINVAL, "ctx or out is NULL");
     mpmq_status r = check_spec(c, spec);
@@ -912,6 +917,15 @@ mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
     out->recomputed = run.recomputed;
     out->states = run.max_live + 1;
     return MPMQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
+                         float *lambda0, mpmq_adjoint_result *out) {
+    return adjoint_impl(c, spec, workspace, workspace_bytes, lambda0, out);
 }
 
 }  // extern "C"

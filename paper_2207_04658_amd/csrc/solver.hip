@@ -94,3 +94,75 @@ extern "C" mpmq_status mpmq_solve_scheme(const mpmq_solve_input *in, mpmq_solve_
     out->total_bits = mem;
     return MPMQ_OK;
 }
+
+// Alg. 1 from a recorded run (see mpmq_auto_scheme in mpmq.h): ranges
+// widened about their centre (Sec. 3.2), P_h = particles x components,
+// then the closed-form widths above.
+extern "C" mpmq_status mpmq_auto_scheme(const mpmq_scheme *base, const mpmq_adjoint_result *adj,
+                                        const mpmq_auto_input *in, mpmq_field_scheme *out_fields,
+                                        mpmq_solve_output *solved) {
+    auto bad = [](const char *m) {
+        g_solver_error = m;
+        return MPMQ_EINVAL;
+    };
+    if (!base || !base->fields || !adj || !in || !out_fields) return bad("base, adj, in and out_fields are required");
+    if (base->dim != 2 && base->dim != 3) return bad("base scheme dim must be 2 or 3");
+    if (base->n_fields != 4) return bad("base scheme must list 4 fields");
+    if (in->n_particles < 1) return bad("n_particles must be >= 1");
+    if (!(in->range_factor >= 1.0) || !std::isfinite(in->range_factor)) return bad("range_factor must be finite and >= 1");
+    const int dim = base->dim;
+    // slot of each base field (F and J share slot 3), each slot once
+    int slot_field[4] = {-1, -1, -1, -1};
+    for (int i = 0; i < 4; ++i) {
+        const int f = base->fields[i].field;
+        if (f < MPMQ_FIELD_X || f > MPMQ_FIELD_J) return bad("unknown field in base scheme");
+        const int sl = f == MPMQ_FIELD_J ? 3 : f;
+        if (slot_field[sl] >= 0) return bad("base scheme lists a field twice");
+        slot_field[sl] = i;
+    }
+    double P[4], g[4], R[4], lo[4], hi[4];
+    for (int sl = 0; sl < 4; ++sl) {
+        const int f = base->fields[slot_field[sl]].field;
+        const int nc = (f == MPMQ_FIELD_X || f == MPMQ_FIELD_V) ? dim : f == MPMQ_FIELD_J ? 1 : dim * dim;
+        if (!std::isfinite(adj->lo[sl]) || !std::isfinite(adj->hi[sl]) || adj->hi[sl] < adj->lo[sl])
+            return bad("recorded ranges must be finite with lo <= hi");
+        const double mid = 0.5 * (adj->lo[sl] + adj->hi[sl]);
+        // a constant field (zero recorded width) gets +-2^-20 max(1, |centre|)
+        const double half = std::fmax(0.5 * (adj->hi[sl] - adj->lo[sl]) * in->range_factor,
+                                      std::ldexp(std::fmax(1.0, std::fabs(mid)), -20));
+        lo[sl] = mid - half;
+        hi[sl] = mid + half;
+        P[sl] = (double)in->n_particles * nc;
+        g[sl] = adj->g[sl];
+        R[sl] = hi[sl] - lo[sl];
+    }
+    double delta[4], bcont[4];
+    int32_t bits[4];
+    mpmq_solve_output o{delta, bcont, bits, 0.0, 0.0};
+    const mpmq_solve_input si{in->mode, 4, in->min_bits, in->max_bits, in->eps, adj->z, P, g, R};
+    const mpmq_status st = mpmq_solve_scheme(&si, &o);
+    if (st != MPMQ_OK) return st;
+    for (int sl = 0; sl < 4; ++sl) {
+        const int i = slot_field[sl];
+        const mpmq_field_scheme &b = base->fields[i];
+        mpmq_field_scheme &f = out_fields[i];
+        f.field = b.field;
+        f.kind = MPMQ_FIXED;
+        f.bits = bits[sl];
+        f.exp_bits = 0;
+        f.dither = b.dither;
+        f.flags = b.flags & MPMQ_REL_IDENTITY;
+        f.lo = lo[sl];
+        f.hi = hi[sl];
+        if (solved) {
+            if (solved->delta) solved->delta[sl] = delta[sl];
+            if (solved->b_cont) solved->b_cont[sl] = bcont[sl];
+            if (solved->bits) solved->bits[sl] = bits[sl];
+        }
+    }
+    if (solved) {
+        solved->expected_error = o.expected_error;
+        solved->total_bits = o.total_bits;
+    }
+    return MPMQ_OK;
+}

@@ -88,9 +88,15 @@ template <int DIM, int MAT>
 __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
                                              const float *C, const float *F, const int *origin,
                                              unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
-                                             uint32_t *__restrict__ flags, uint32_t &fallback) {
+                                             uint32_t *__restrict__ flags, uint32_t &fallback,
+                                             uint32_t &clamped) {
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
-    constexpr float LIM = 4096.0f;  // |q|, |a_b| <= 2^12 keeps every term below 2^19
+    // |q|, |a_b| <= 2^12 keeps a node value q + sum_b a_b o_b below 2^15
+    // (2^47 in fixed point), so a node sum of up to 2^16 contributions stays
+    // inside int64.  A particle with a larger term is clamped and counted
+    // (ST_CLAMP); the count sees finite values only: a NaN is clamped too,
+    // and is counted by the encoder's NaN counter where it is stored.
+    constexpr float LIM = 4096.0f;
     int base[DIM];
     float fx[DIM];
     stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
@@ -135,17 +141,22 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
     }
     // node value = w (q + sum_b a_b o_b), q = v - (A/m) f dx, a_b = (A/m)[:, b] dx, scaled by 2^32
     double q[DIM], ac[DIM][DIM];  // ac[b][a]
+    float big = 0.0f;  // largest |term| before clamping
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         float t = v[a];
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            const float ab = fminf(fmaxf(Am[a * DIM + b] * P.dx, -LIM), LIM);
+            const float ab0 = Am[a * DIM + b] * P.dx;
+            big = fmaxf(big, fabsf(ab0));
+            const float ab = fminf(fmaxf(ab0, -LIM), LIM);
             ac[b][a] = (double)ab * FIX_ONE;
             t -= ab * fx[b];
         }
+        big = fmaxf(big, fabsf(t));
         q[a] = (double)fminf(fmaxf(t, -LIM), LIM) * FIX_ONE;
     }
+    clamped += (big > LIM) ? 1u : 0u;
     bool in_tile = true;
     int l[DIM];
 #pragma unroll
@@ -357,7 +368,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
     __shared__ uint32_t touched[27];
     if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const uint32_t nit = *n_items;
-    uint32_t fallback = 0;
+    uint32_t fallback = 0, clamped = 0;
     const ItemWalk walk(nit);
     for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
         const WorkItem it = items[item];
@@ -370,12 +381,13 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
             double xd[DIM];
             float v[DIM], C[D2], F[nc3<DIM, MAT>()];
             decode_all<DIM, float, MAT>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
-            p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback);
+            p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback, clamped);
         }
         __syncthreads();
         tile_flush<DIM>(P, origin, acc, gout, flags, touched);
     }
     add_stat(stats, ST_FALLBACK, fallback);
+    add_stat(stats, ST_CLAMP, clamped);
 }
 
 
@@ -504,7 +516,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
     __shared__ uint32_t touched[27];
     if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const uint32_t nit = *n_items;
-    uint32_t fallback = 0;
+    uint32_t fallback = 0, clamped = 0;
     LaneStats ls;
     ls.clear();
     const ItemWalk walk(nit);
@@ -600,7 +612,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             float qv[DIM], qC[D2], qF[N3];
             encode_record<DIM, RS, MAT>(sch, xn, nv, Cn, Fn, rnd, os, ls, qx, qv, qC, qF);
             // P2G of the stored (quantized) state for the next substep (Eq. 1)
-            if (do_p2g) p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback);
+            if (do_p2g) p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback, clamped);
         }
         __syncthreads();
         // the velocity tile is free now: it holds the flush's node table
@@ -612,6 +624,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
         }
     }
     add_stat(stats, ST_FALLBACK, fallback);
+    add_stat(stats, ST_CLAMP, clamped);
 }
 
 

@@ -36,3 +36,54 @@ def by_id(arr, ids):
     out = np.empty_like(arr)
     out[..., ids] = arr
     return out
+
+
+def _bits(words, off, nbits):
+    """Bits [off, off + nbits) of every record (words: uint32 [W, n])."""
+    w = np.asarray(words).astype(np.uint64)
+    lo = w[off // 32]
+    hi = w[off // 32 + 1] if off // 32 + 1 < w.shape[0] else np.zeros_like(lo)
+    return (((lo | (hi << np.uint64(32))) >> np.uint64(off % 32)) & np.uint64((1 << nbits) - 1)).astype(np.int64)
+
+
+def field_steps_per_particle(orc, scheme, words):
+    """Quantization step of each particle's stored value, per field (slot
+    order x, v, C, F/J): Delta for a fixed-point field, 2^(E - m + 1) from the
+    stored exponent for a shared-exponent field, the float32 spacing at the
+    stored value for a raw field (None: taken from the values)."""
+    import math
+    _, fo, _, _ = orc.layout(scheme)
+    names = ["x", "v", "C", "J" if any(f["field"] == "J" for f in scheme["fields"]) else "F"]
+    out = {}
+    for f in scheme["fields"]:
+        slot = names.index(f["field"])
+        if f["kind"] == "fixed":
+            out[f["field"]] = np.full(words.shape[1], (f["hi"] - f["lo"]) * 2.0 ** -f["bits"])
+        elif f["kind"] == "shared_exp":
+            emax = math.ceil(math.log2(f["hi"]))
+            emin = emax - (2 ** f["exp_bits"] - 1)
+            e = _bits(words, int(fo[slot]), f["exp_bits"]) + emin
+            out[f["field"]] = np.ldexp(1.0, (e - (f["bits"] - 1)).astype(np.int32))
+        else:
+            out[f["field"]] = None
+    return out
+
+
+def lsb_differences(orc, scheme, gw, gids, ow, oids):
+    """Decoded GPU and oracle states (ordered by original particle) and, per
+    field, |gpu - oracle| in units of the larger of the two quantization
+    steps of each particle's stored value.  Returns (x difference in domain
+    units [dim, n], {field: LSB differences [ncomp, n]})."""
+    g = [by_id(a, gids) for a in orc.decode(scheme, gw)]
+    o = [by_id(a, oids) for a in orc.decode(scheme, ow)]
+    sg = field_steps_per_particle(orc, scheme, gw)
+    so = field_steps_per_particle(orc, scheme, ow)
+    names = ["x", "v", "C", "J" if any(f["field"] == "J" for f in scheme["fields"]) else "F"]
+    lsb = {}
+    for i, f in enumerate(names):
+        if sg[f] is None:
+            step = np.maximum(np.spacing(np.abs(o[i]).astype(np.float32)).astype(np.float64), 2.0 ** -149)
+        else:
+            step = np.maximum(by_id(sg[f], gids), by_id(so[f], oids))[None, :]
+        lsb[f] = np.abs(g[i] - o[i]) / step
+    return np.abs(g[0] - o[0]), lsb

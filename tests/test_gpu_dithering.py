@@ -1,0 +1,52 @@
+"""Dithering at simulation scale (Sec. 5; the round-up / round-down study of
+Sec. 8.1): on an elastic block that hits the floor and rings, stored at
+coarse widths, round-to-nearest stores lock onto lattice points (F and C
+mostly round down) while dithered stores round up and down about equally
+often.  The GPU's encoder counters (mpmq_set_stats(1)) are compared with the
+oracle's on the same run and with those two properties."""
+import numpy as np
+import pytest
+
+import workloads as WL
+from gpu_common import gpu_context, note, oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+
+def ratio(st):
+    up = sum(st[f]["up"] for f in "xvCF")
+    down = sum(st[f]["down"] for f in "xvCF")
+    return up / down
+
+
+@pytest.mark.parametrize("dither", [False, True])
+def test_round_up_down_counts(gpu_lib, orc, dither):
+    sc = WL.bounce_block(seed=1, dither=dither)
+    steps = sc["steps"]
+    note(f"dithering counters dither={dither} n={sc['n']} steps={steps}")
+    ctx = gpu_context(gpu_lib, sc)
+    ctx.set_stats(1)
+    ctx.reset_stats()
+    ctx.step(steps)
+    g = ctx.stats()
+    sim, _, _ = oracle_sim(orc, sc)
+    sim.step(steps)
+    o = sim.stats()
+    sim.close()
+    ctx.close()
+    print(f"dither={dither}: gpu ratio {ratio(g):.4f}, oracle ratio {ratio(o):.4f}")
+    for f in "xvCF":
+        total = o[f]["up"] + o[f]["down"]
+        assert g[f]["up"] + g[f]["down"] + g[f]["sat"] == total + o[f]["sat"] == sc["n"] * steps * (
+            2 if f in "xv" else 4)
+        # same run: the counts differ only where FP32 arithmetic flips a
+        # rounding that lies within its error of a lattice point (and the
+        # trajectories then drift apart by a few codes)
+        assert abs(g[f]["up"] - o[f]["up"]) <= 0.01 * total, (f, g[f], o[f])
+        assert g[f]["sat"] == 0 and o[f]["sat"] == 0
+    if dither:
+        assert abs(ratio(g) - 1.0) <= 0.03 and abs(ratio(o) - 1.0) <= 0.03
+    else:
+        assert ratio(g) < 0.85 and ratio(o) < 0.85
+        for f in "CF":
+            assert g[f]["up"] < 0.8 * g[f]["down"], f

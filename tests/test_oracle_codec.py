@@ -95,6 +95,38 @@ def test_fp32_layout_size(orc, dim, nbytes):
     assert 4 * W == nbytes and total == 8 * nbytes
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_raw_f32_codec_is_the_float32_bit_pattern(orc, dim):
+    """RAW_F32 stores each component's IEEE float32 bits (F - I on the
+    diagonal of a REL_IDENTITY field, formed in binary64 and rounded once);
+    decoding gives the float32 value back (+ 1 on that diagonal).  Checked
+    against NumPy's own float32 casts and bit views, in placement order,
+    including signed zeros, subnormals, infinities and NaN."""
+    rng = np.random.default_rng(7 + dim)
+    n = 257
+    x, v, C, F = WL.random_state(rng, dim, n, c_scale=1e3, f_scale=0.5)
+    special = np.array([0.0, -0.0, 1e-40, -3e-39, np.inf, -np.inf, np.nan, 3.4e38, 1.0 + 2 ** -23, 1e-8],
+                       dtype=np.float32)
+    v[0, :special.size] = special
+    C[-1, :special.size] = special[::-1]
+    F[0, :special.size] = special
+    scheme = WL.scheme_fp32(dim, 0)
+    scheme["fields"] = [scheme["fields"][i] for i in (2, 0, 3, 1)]  # placement C, x, F, v
+    scheme["fields"][2]["rel_identity"] = True
+    words, st = orc.encode(scheme, x, v, C, F)
+    diag = np.array([(i % (dim + 1)) == 0 for i in range(dim * dim)])
+    Frel = F.astype(np.float64) - np.where(diag[:, None], 1.0, 0.0)
+    expect = np.concatenate([C, x, Frel.astype(np.float32), v], axis=0).view(np.uint32)
+    assert words.shape == expect.shape and np.array_equal(words, expect)
+    assert all(st[f]["sat"] == 0 and st[f]["nan"] == 0 for f in "xvCF")
+    dx, dv, dC, dF = orc.decode(scheme, words)
+    for got, ref in ((dx, x), (dv, v), (dC, C)):
+        same = (got == ref.astype(np.float64)) | (np.isnan(got) & np.isnan(ref))
+        assert same.all()
+    refF = Frel.astype(np.float32).astype(np.float64) + np.where(diag[:, None], 1.0, 0.0)
+    assert (((dF == refF) | (np.isnan(dF) & np.isnan(refF)))).all()
+
+
 def test_config_record_sizes(orc):
     assert orc.layout(WL.scheme_c1(2))[3] == 7       # 200 bits
     assert orc.layout(WL.scheme_c1(3, True))[3] == 13  # 396 bits
@@ -349,3 +381,25 @@ def test_philox_statistics(orc):
     u = halves / 65536.0
     r = np.corrcoef(u[:-1], u[1:])[0, 1]
     assert abs(r) < 4 / np.sqrt(u.size)
+
+
+@pytest.mark.parametrize("dither", [False, True])
+def test_oracle_round_up_down_ratio(orc, dither):
+    """Simulation-scale dithering (Sec. 5, the round-up / round-down study of
+    Sec. 8.1): an elastic block that hits the floor and rings, stored at
+    coarse widths.  Round to nearest locks C and F onto lattice points
+    (mostly rounding down: overall ratio ~0.75); dithered stores round up
+    and down about equally often (ratio within 3 % of 1)."""
+    sc = WL.bounce_block(seed=1, dither=dither)
+    w, _ = orc.encode(sc["scheme"], *sc["state"], 0, 2)
+    sim = orc.Sim(sc["scheme"], sc["params"], w)
+    sim.step(sc["steps"])
+    st = sim.stats()
+    sim.close()
+    up = sum(st[f]["up"] for f in "xvCF")
+    down = sum(st[f]["down"] for f in "xvCF")
+    if dither:
+        assert abs(up / down - 1.0) <= 0.03
+    else:
+        assert up / down < 0.85
+        assert st["F"]["up"] < 0.8 * st["F"]["down"] and st["C"]["up"] < 0.8 * st["C"]["down"]

@@ -337,6 +337,56 @@ def random_state(rng, dim, n, x_lo=0.2, x_hi=0.8, v_scale=1.0, c_scale=5.0, f_sc
     return x, v, C, F
 
 
+def bounce_block(seed=0, dither=True, n=4096, steps=400):
+    """2D elastic block [0.3, 0.5] x [0.04, 0.24] thrown at the floor with
+    v = (0, -2): it hits the wall band at once and rings, so every field
+    keeps changing by amounts comparable to its quantization step.  Coarse
+    scheme (the regime of the paper's dithering study, Sec. 8.1): x 16-bit,
+    v 10-bit in [-20, 20], C 10-bit in [-200, 200], F 10-bit (F - I in
+    [-1, 1]); 128^2 grid, dt = 1e-4, sorted every 10 steps."""
+    rng = np.random.default_rng(seed)
+    x = np.stack([0.3 + 0.2 * rng.random(n), 0.04 + 0.2 * rng.random(n)]).astype(np.float32)
+    v, C, F = rest_state(2, n)
+    v[1] = -2.0
+    sch = {"dim": 2, "seed": seed, "fields": [
+        fixed("x", 16, 0.0, 1.0, dither), fixed("v", 10, -20.0, 20.0, dither),
+        fixed("C", 10, -200.0, 200.0, dither), fixed("F", 10, -1.0, 1.0, dither, rel_identity=True)]}
+    return {"name": "bounce", "scheme": sch, "steps": steps, "n": n,
+            "params": params(2, 128, 1e-4, 0.04 / n, sort_every=10), "state": (x, v, C, F)}
+
+
+def inverted_scene(dim, seed=0, n=3000, grid_res=32, frac=0.4):
+    """Elastic particles with random deformation gradients of which about
+    `frac` are inverted (det F < 0) or flattened (one singular value near
+    zero): F = Q diag(s) P^T with random rotations Q, P and singular values
+    in [0.6, 1.4], the last one negated (inverted) or set to 1e-4
+    (flattened).  Particles uniform in [0.3, 0.7]^dim, velocities U(-0.5,
+    0.5), C = 0, raw float32 layout (so the initial encode is exact)."""
+    rng = np.random.default_rng([seed, 9])
+    x = rng.uniform(0.3, 0.7, (dim, n)).astype(np.float32)
+    v = rng.uniform(-0.5, 0.5, (dim, n)).astype(np.float32)
+    C = np.zeros((dim * dim, n), dtype=np.float32)
+
+    def rotation():
+        q, r = np.linalg.qr(rng.standard_normal((dim, dim)))
+        q = q * np.sign(np.diag(r))[None, :]
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        return q
+
+    F = np.empty((dim * dim, n), dtype=np.float32)
+    kind = rng.random(n)
+    for p in range(n):
+        s = rng.uniform(0.6, 1.4, dim)
+        if kind[p] < frac * 0.75:
+            s[-1] = -s[-1]
+        elif kind[p] < frac:
+            s[-1] = 1e-4
+        F[:, p] = (rotation() @ np.diag(s) @ rotation().T).reshape(-1)
+    return {"name": f"inverted{dim}d", "scheme": scheme_fp32(dim, seed), "steps": 1, "n": n,
+            "params": params(dim, grid_res, 1e-4, 0.4 ** dim / n), "state": (x, v, C, F)}
+
+
 def random_scheme(rng, dim, seed=0):
     """A random valid scheme: 12-24 bits per field, random dither and kinds."""
     fields = []
