@@ -13,12 +13,16 @@ stream:
 
 Bars.  x: within 1e-4 of the unit domain (the metric's tolerance).  v, C, F:
 compared per component in units of the quantization step of the stored
-value (the larger of the two sides' steps for a shared exponent).  A store
-whose unquantized value lies within FP32 error of a rounding boundary may
-round the other way on the GPU (one code); such a flip perturbs the grid
-momenta around it by a fraction of a code, so later flips cluster near
-earlier ones.  The bars: at least 99 % of components identical or one code
-apart, and no component more than 8 codes apart.
+value (the larger of the two sides' steps for a shared exponent), or of the
+change that a one-code flip of v induces (gpu_common.comparison_units)
+where that is larger: a store whose unquantized value lies within FP32
+error of a rounding boundary may round the other way on the GPU, and a
+one-code change of v moves C' of the particles around it by up to
+(4 / dx) Delta_v, which is hundreds of codes of a 16-bit C, and F
+integrates dt C' F over the substeps.  Such flips
+perturb the grid momenta around them, so later flips cluster near earlier
+ones.  The bars: at least 99 % of components within one unit, and no
+component more than 8 units apart.
 """
 import numpy as np
 import pytest
@@ -58,7 +62,7 @@ def c2_cube_oracle(orc):
     sim = orc.Sim(sc["scheme"], sc["params"], w0)
     out = {}
     for t in (50, 100):
-        sim.step(t - sim.step_count())
+        sim.step(t - sim.step_count)
         out[t] = (sim.words(), sim.ids(), sim.stats())
     sim.close()
     return sc, w0, out
@@ -76,7 +80,7 @@ def test_c2_cube_100_steps(gpu_lib, orc, c2_cube_oracle, specialized):
     for t in (50, 100):
         ctx.step(t - ctx.step_count())
         ow, oids, ost = ref[t]
-        dx, lsb = lsb_differences(orc, sc["scheme"], ctx.words(), ctx.ids(), ow, oids)
+        dx, lsb = lsb_differences(orc, sc["scheme"], ctx.words(), ctx.ids(), ow, oids, sc["params"], t)
         _check(f"c2 cube step {t} spec={specialized}", dx, lsb)
     st = ctx.stats()
     assert st["sorts"] == 10 and st["clamped"] == 0
@@ -106,7 +110,7 @@ def test_c3_cube_10_steps(gpu_lib, orc, c3_cube_oracle, specialized):
         ctx.specialize(True)
     assert np.array_equal(ctx.words(), w0)
     ctx.step(10)
-    dx, lsb = lsb_differences(orc, sc["scheme"], ctx.words(), ctx.ids(), ow, oids)
+    dx, lsb = lsb_differences(orc, sc["scheme"], ctx.words(), ctx.ids(), ow, oids, sc["params"], 10)
     _check(f"c3 cube 0 step 10 spec={specialized}", dx, lsb)
     st = ctx.stats()
     assert st["clamped"] == 0 and all(st[f]["nan"] == 0 for f in "xvCF")

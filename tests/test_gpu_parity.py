@@ -151,10 +151,11 @@ def test_small_scene_trajectory(gpu_lib, orc, dim, dither):
             assert same > 0.9, same
         # every field, in units of its quantization step (see test_gpu_horizon
         # for the reasoning behind the bars)
-        dx, lsb = lsb_differences(orc, sc["scheme"], ctx.words(), ctx.ids(), sim.words(), sim.ids())
+        dx, lsb = lsb_differences(orc, sc["scheme"], ctx.words(), ctx.ids(), sim.words(), sim.ids(), sc["params"],
+                                  sim.step_count)
         assert np.max(dx) <= 1e-4, np.max(dx)
         for f in "vCF":
-            print(f"dim {dim} dither {dither} step {sim.step_count()} {f}: "
+            print(f"dim {dim} dither {dither} step {sim.step_count} {f}: "
                   f"<=1 code {np.mean(lsb[f] <= 1 + 1e-9):.5f} max {np.max(lsb[f]):.1f}")
             assert np.mean(lsb[f] <= 1 + 1e-9) >= 0.99, f
             assert np.max(lsb[f]) <= 8, f
