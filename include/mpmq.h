@@ -280,6 +280,23 @@ mpmq_status mpmq_adjoint_workspace(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec,
 mpmq_status mpmq_adjoint(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
                          float *lambda0, mpmq_adjoint_result *out);
 
+/* Allocation-free adjoint, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): mpmq_adjoint with
+ * the workspace taken from a library-owned static device array of
+ * MPMQ_STATIC_WORKSPACE_BYTES (64 MiB) on the current device, which must be
+ * the context's device.  Each device that runs this call holds its own
+ * array until the process ends.  The call itself performs no device
+ * allocation or free.  ENOMEM, with a message naming both sizes, when
+ * mpmq_adjoint_workspace for spec exceeds the array; EDEVICE when the
+ * array's address cannot be obtained.  Every call on one device shares
+ * that device's array, which keeps the last call's contents (the call
+ * clears what it needs cleared): calls that overlap on one device -- from
+ * different threads, contexts or streams -- race and must be serialized by
+ * the caller.  lambda0 (caller-owned output) and out as in mpmq_adjoint. */
+#define MPMQ_STATIC_WORKSPACE_BYTES (64ll << 20)
+mpmq_status mpmq_adjoint_static(mpmq_ctx *ctx, const mpmq_adjoint_spec *spec, float *lambda0,
+                                mpmq_adjoint_result *out);
+
 /* ---- Automatic quantization solver (Sec. 4, Eqs. 6-10, Alg. 1) ----
  * Host-only; touches no device.  Per data type h: P_h variables, the
  * accumulated squared gradient g_h (Eq. 8; mpmq_adjoint's g), the range

@@ -143,6 +143,7 @@ def load(path: str = LIB_PATH):
         "mpmq_kernel_times": [P, ct.POINTER(mpmq_kernel_time), ct.c_int32, ct.POINTER(ct.c_int32)],
         "mpmq_adjoint_workspace": [P, ct.POINTER(mpmq_adjoint_spec), ct.POINTER(ct.c_int64)],
         "mpmq_adjoint": [P, ct.POINTER(mpmq_adjoint_spec), P, ct.c_int64, P, ct.POINTER(mpmq_adjoint_result)],
+        "mpmq_adjoint_static": [P, ct.POINTER(mpmq_adjoint_spec), P, ct.POINTER(mpmq_adjoint_result)],
         "mpmq_solve_scheme": [ct.POINTER(mpmq_solve_input), ct.POINTER(mpmq_solve_output)],
         "mpmq_auto_scheme": [ct.POINTER(mpmq_scheme), ct.POINTER(mpmq_adjoint_result), ct.POINTER(mpmq_auto_input),
                              ct.POINTER(mpmq_field_scheme), ct.POINTER(mpmq_solve_output)],
@@ -165,7 +166,7 @@ def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
             "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
             "mpmq_specialize",
-            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_solve_scheme", "mpmq_auto_scheme", "mpmq_solver_error", "mpmq_error_string",
+            "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_adjoint_static", "mpmq_solve_scheme", "mpmq_auto_scheme", "mpmq_solver_error", "mpmq_error_string",
             "mpmq_last_error"]
 
 
@@ -220,6 +221,10 @@ def mpmq_query_sizes(scheme: dict, params: dict, capacity: int) -> dict:
     out = mpmq_sizes()
     _check(load().mpmq_query_sizes(ct.byref(s), ct.byref(p), int(capacity), ct.byref(out)))
     return {k: getattr(out, k) for k, _ in mpmq_sizes._fields_}
+
+
+# bytes of the library's static adjoint workspace (MPMQ_STATIC_WORKSPACE_BYTES)
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 class Context:
@@ -373,6 +378,28 @@ class Context:
         if lam0 is not None:
             out["lambda0"] = lam0
         return out
+
+    def adjoint_static(self, steps, objective="com", axis=1, checkpoint_every=8, lambda0=None):
+        """mpmq_adjoint_static: the adjoint with the library's static device
+        workspace (STATIC_WORKSPACE_BYTES); nothing is allocated for the call.
+        lambda0: optional caller-owned float32 tensor [2d + 2d^2, n] on the
+        context's device that receives lambda_0.  Returns the dict of
+        adjoint() (without workspace_bytes)."""
+        import torch
+        s = mpmq_adjoint_spec(OBJECTIVES[objective], int(axis), int(steps), int(checkpoint_every))
+        if lambda0 is not None:
+            rows = 2 * self.dim + self.dim * self.dim + self.nc3
+            if (tuple(lambda0.shape) != (rows, self.n) or lambda0.dtype != torch.float32
+                    or not lambda0.is_contiguous() or lambda0.device != self.device):
+                raise ValueError(f"lambda0 must be a contiguous float32 [{rows}, {self.n}] tensor on {self.device}")
+        res = mpmq_adjoint_result()
+        _check(load().mpmq_adjoint_static(self._h, ct.byref(s),
+                                          ct.c_void_p(lambda0.data_ptr()) if lambda0 is not None else None,
+                                          ct.byref(res)), self._h)
+        names = ["x", "v", "C", self.f3]
+        return {"z": res.z, "G": {names[i]: res.G[i] for i in range(4)}, "g": {names[i]: res.g[i] for i in range(4)},
+                "lo": {names[i]: res.lo[i] for i in range(4)}, "hi": {names[i]: res.hi[i] for i in range(4)},
+                "recomputed": res.recomputed, "states": res.states}
 
     def close(self):
         if getattr(self, "_h", None):

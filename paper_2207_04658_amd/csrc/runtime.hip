@@ -9,6 +9,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -926,6 +927,58 @@ extern "C" {
 mpmq_status mpmq_adjoint(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *workspace, int64_t workspace_bytes,
                          float *lambda0, mpmq_adjoint_result *out) {
     return adjoint_impl(c, spec, workspace, workspace_bytes, lambda0, out);
+}
+
+}  // extern "C"
+
+// ---- allocation-free adjoint ----
+// A file-scope device array serves as the adjoint workspace of
+// mpmq_adjoint_static.  In host code the name `scratch` denotes a host-side
+// stand-in, not a device address: the device address is obtained once per
+// device with hipGetSymbolAddress (that device current) and only that
+// address is handed to the kernels.
+static __device__ __align__(256) unsigned char scratch[MPMQ_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+mpmq_status static_workspace(mpmq_ctx *c, void **out) {
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev), "static workspace: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, MPMQ_EDEVICE, "static workspace: device index out of range");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "static workspace: hipGetSymbolAddress");
+        if (!p) return fail(c, MPMQ_EDEVICE, "static workspace: no device address");
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return MPMQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpmq_status mpmq_adjoint_static(mpmq_ctx *c, const mpmq_adjoint_spec *spec, float *lambda0,
+                                mpmq_adjoint_result *out) {
+    if (!c || !out) return fail(c, MPMQ_EINVAL, "ctx or out is NULL");
+    mpmq_status r = check_spec(c, spec);
+    if (r != MPMQ_OK) return r;
+    const int64_t need = adj_layout(c, adj_plan(spec->steps, spec->checkpoint_every)).total;
+    if (need > (int64_t)MPMQ_STATIC_WORKSPACE_BYTES)
+        return fail(c, MPMQ_ENOMEM, "adjoint needs a workspace of " + std::to_string(need) +
+                                        " bytes; the static workspace holds " +
+                                        std::to_string((int64_t)MPMQ_STATIC_WORKSPACE_BYTES));
+    void *ws = nullptr;
+    if ((r = static_workspace(c, &ws)) != MPMQ_OK) return r;
+    return adjoint_impl(c, spec, ws, (int64_t)MPMQ_STATIC_WORKSPACE_BYTES, lambda0, out);
 }
 
 }  // extern "C"
