@@ -91,13 +91,32 @@ __device__ __forceinline__ uint32_t ld_row(const uint32_t *words, int64_t cap, i
     return *reinterpret_cast<const uint32_t *>(row + p4);
 }
 
+// Where a decode reads the record from: the rows in global memory, or
+// registers holding rows loaded ahead of time (r[k] = row k; a specialized
+// build indexes it with compile-time constants only, so it stays in
+// registers).
+struct GlobalRows {
+    const uint32_t *words;
+    int64_t cap;
+    uint32_t p4;
+    __device__ __forceinline__ uint32_t row(int k) const { return ld_row(words, cap, k, p4); }
+};
+struct RegRows {
+    const uint32_t *r;
+    __device__ __forceinline__ uint32_t row(int k) const { return r[k]; }
+};
+
+template <typename Src>
+__device__ __forceinline__ uint32_t get_comp(const Src &src, int o, int bits, uint32_t mask) {
+    const int k = o >> 5, sh = o & 31;
+    const uint32_t lo = src.row(k);
+    uint32_t hi = 0u;
+    if (sh + bits > 32) hi = src.row(k + 1);
+    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)sh) & mask;
+}
 __device__ __forceinline__ uint32_t get_comp(const uint32_t *words, int64_t cap, uint32_t p4, int o, int bits,
                                              uint32_t mask) {
-    const int k = o >> 5, sh = o & 31;
-    const uint32_t lo = ld_row(words, cap, k, p4);
-    uint32_t hi = 0u;
-    if (sh + bits > 32) hi = ld_row(words, cap, k + 1, p4);
-    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)sh) & mask;
+    return get_comp(GlobalRows{words, cap, p4}, o, bits, mask);
 }
 
 // Encoder output: codes arrive in placement order and are appended to a
@@ -215,13 +234,31 @@ __device__ __forceinline__ uint32_t enc_fixed(const FieldRef f, double val, doub
     const double t = (val - f->lo) * f->inv;
     const double sv = fma(h, XI_SCALE, t);
     const double fl = floor(sv);
-    // clamp to [0, maxc] (fmax takes a NaN to 0); a value the clamp changed
-    // saturated.  Selects rather than branches: the counters are per-lane.
-    const bool nan = !(sv == sv), below = fl < 0.0, above = fl > f->maxc;
-    const uint32_t code = (uint32_t)fmin(fmax(fl, 0.0), f->maxc);  // fmax takes a NaN to 0
-    ls.nan += nan ? 1u << (8 * fid) : 0u;
-    ls.sat += (below || above) ? 1u << (8 * fid) : 0u;
-    if (RS) ls.ud[fid] += (nan || below || above) ? 0u : (fl > floor(t)) ? 1u : 0x10000u;
+    if (RS) {
+        // clamp to [0, maxc] (fmax takes a NaN to 0); a value the clamp
+        // changed saturated.  Selects rather than branches: the counters are
+        // per-lane.
+        const bool nan = !(sv == sv), below = fl < 0.0, above = fl > f->maxc;
+        const uint32_t code = (uint32_t)fmin(fmax(fl, 0.0), f->maxc);
+        ls.nan += nan ? 1u << (8 * fid) : 0u;
+        ls.sat += (below || above) ? 1u << (8 * fid) : 0u;
+        ls.ud[fid] += (nan || below || above) ? 0u : (fl > floor(t)) ? 1u : 0x10000u;
+        return code;
+    }
+    // fl in [0, maxc] holds for every lane unless the wave takes the branch:
+    // as bit patterns, the non-negative doubles up to maxc are exactly those
+    // not above maxc's (a negative value, -0, NaN or inf compares above), so
+    // one unsigned compare decides, and the exact clamp and the counters run
+    // only in a wave that holds an out-of-range value.
+    uint32_t code = (uint32_t)fl;
+    const uint64_t out = __ballot((uint64_t)__double_as_longlong(fl) >
+                                  (uint64_t)__double_as_longlong(f->maxc));
+    if (__builtin_expect(out != 0ull, 0)) {
+        const bool nan = !(sv == sv), below = fl < 0.0, above = fl > f->maxc;
+        code = (uint32_t)fmin(fmax(fl, 0.0), f->maxc);  // fmax takes a NaN to 0
+        ls.nan += nan ? 1u << (8 * fid) : 0u;
+        ls.sat += (below || above) ? 1u << (8 * fid) : 0u;
+    }
     return code;
 }
 
@@ -235,10 +272,12 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
     const int m1 = f->bits - 1;
     const double qmax = (double)f->mag_mask;
     double M = 0.0;
+    uint64_t nan_lanes = 0ull;  // lanes of the wave with a NaN component
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const double x = (double)val[c];
-        ls.nan += (x == x) ? 0u : 1u << (8 * slot_of<FID>());
+        if (RS) ls.nan += (x == x) ? 0u : 1u << (8 * slot_of<FID>());
+        else nan_lanes |= __ballot(!(val[c] == val[c]));
         M = fmax(M, fabs(x));  // fmax ignores a NaN operand
     }
     int E;
@@ -249,6 +288,7 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
     // arithmetic; the loop keeps the definition literal); the rounded
     // magnitudes of the last pass are the codes
     double tq[NC], qq[NC];
+    double qtop_end;
     for (;;) {
         double qtop = 0.0;
 #pragma unroll
@@ -260,18 +300,36 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
             qq[c] = floor(fma(h, XI_SCALE, tq[c]));
             qtop = fmax(qtop, qq[c]);
         }
+        qtop_end = qtop;
         if (!(qtop > qmax && E < f->emax)) break;
         E += 1;
     }
     os.emit((uint32_t)(E - f->emin), f->exp_bits);
+    // A magnitude can exceed qmax only where the loop above stopped at E_max
+    // with qtop > qmax: without such a lane (and without a NaN) in the wave
+    // the codes need neither the clamp nor the counters.
+    bool slow = true;
+    if (!RS) {
+        slow = __ballot(qtop_end > qmax) != 0ull || nan_lanes != 0ull;
+        if (__builtin_expect(slow, 0)) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                ls.nan += (val[c] == val[c]) ? 0u : 1u << (8 * slot_of<FID>());
+        }
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const double t = tq[c];
         const double q = qq[c];
-        const bool above = q > qmax;
-        const uint32_t qc = (uint32_t)fmin(q, qmax);  // q >= 0
-        ls.sat += above ? 1u << (8 * slot_of<FID>()) : 0u;
-        if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
+        uint32_t qc;
+        if (RS || __builtin_expect(slow, 0)) {
+            const bool above = q > qmax;
+            qc = (uint32_t)fmin(q, qmax);  // q >= 0
+            ls.sat += above ? 1u << (8 * slot_of<FID>()) : 0u;
+            if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
+        } else {
+            qc = (uint32_t)q;  // q <= qmax
+        }
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
         os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);
         if (kF32Decode && is_f32<T>::value && f->f32dec) {
@@ -324,15 +382,14 @@ __device__ __forceinline__ void enc_field(const FieldRef f, const T *val, Draws 
 
 // Decodes field FID exactly in binary64 (identity added back for a
 // REL_IDENTITY field) and rounds once to T.
-template <int DIM, int FID, typename T>
-__device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *words, int64_t cap, uint32_t p4,
-                                          T *out) {
+template <int DIM, int FID, typename T, typename Src>
+__device__ __forceinline__ void dec_field_src(const FieldRef f, const Src &src, T *out) {
 #pragma clang fp contract(off)
     constexpr int NC = ncomp<DIM, FID>();
     if (f->kind == K_FIXED) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const uint32_t u = get_comp(words, cap, p4, f->off + c * f->bits, f->bits, f->mask);
+            const uint32_t u = get_comp(src, f->off + c * f->bits, f->bits, f->mask);
             const bool diag = f->rel && (c % (DIM + 1) == 0);
             if (kF32Decode && is_f32<T>::value && f->f32dec) {
                 const float q = fmaf((float)u, (float)f->delta, (float)f->lo);
@@ -345,16 +402,16 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
     } else if (f->kind == K_RAW) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double q = (double)__uint_as_float(get_comp(words, cap, p4, f->off + 32 * c, 32, 0xffffffffu));
+            const double q = (double)__uint_as_float(get_comp(src, f->off + 32 * c, 32, 0xffffffffu));
             out[c] = (T)((f->rel && (c % (DIM + 1) == 0)) ? q + 1.0 : q);
         }
     } else {
-        const int E = (int)get_comp(words, cap, p4, f->off, f->exp_bits, f->exp_mask) + f->emin;
+        const int E = (int)get_comp(src, f->off, f->exp_bits, f->exp_mask) + f->emin;
         const int m1 = f->bits - 1;
         const int o0 = f->off + f->exp_bits;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const uint32_t q = get_comp(words, cap, p4, o0 + c * f->bits, f->bits, f->mask);
+            const uint32_t q = get_comp(src, o0 + c * f->bits, f->bits, f->mask);
             if (kF32Decode && is_f32<T>::value && f->f32dec) {
                 const float mag = ldexpf((float)(q & f->mag_mask), E - m1);
                 out[c] = (T)(((q >> m1) & 1u) ? -mag : mag);
@@ -367,6 +424,30 @@ __device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *word
 }
 
 
+
+template <int DIM, int FID, typename T>
+__device__ __forceinline__ void dec_field(const FieldRef f, const uint32_t *words, int64_t cap, uint32_t p4,
+                                          T *out) {
+    dec_field_src<DIM, FID, T>(f, GlobalRows{words, cap, p4}, out);
+}
+
+#ifdef MPMQ_SCHEME_CONST
+// Record rows (bit k: word row k) that the bits of a field of the
+// compile-time scheme occupy.
+constexpr uint32_t field_rows(const DevField &f, int nc) {
+    const int nbits = f.kind == K_RAW ? 32 * nc : f.kind == K_SEXP ? f.exp_bits + nc * f.bits : nc * f.bits;
+    uint32_t m = 0u;
+    for (int k = f.off >> 5; k <= (f.off + nbits - 1) >> 5; ++k) m |= 1u << k;
+    return m;
+}
+// Loads the rows of `mask` of slot p4 / 4 into r[] (compile-time indices).
+template <uint32_t MASK>
+__device__ __forceinline__ void load_rows(const uint32_t *words, int64_t cap, uint32_t p4, uint32_t *r) {
+#pragma unroll
+    for (int k = 0; k < MAX_WORDS; ++k)
+        if (MASK & (1u << k)) r[k] = ld_row(words, cap, k, p4);
+}
+#endif
 
 // Decodes the whole record (F3: F for a solid, J for a fluid).
 template <int DIM, typename T, int MAT>
@@ -615,7 +696,9 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
     const float detF = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
                        F[2] * (F[3] * F[7] - F[4] * F[6]);
     const float s3 = n2 * (1.0f / 3.0f);
-    const bool svd = detF <= 1e-3f * s3 * sqrtf(s3);  // NaN F: false (Newton, NaN out)
+    // (a Newton lane then has det F >= 1e-20, so every reciprocal below is
+    // finite; its iterates keep a determinant of at least min(det F, 1))
+    const bool svd = detF <= 1e-3f * s3 * sqrtf(s3) || detF < 1e-20f;  // NaN F: false (Newton, NaN out)
 #pragma unroll
     for (int i = 0; i < 9; ++i) R[i] = svd ? ((i % 4 == 0) ? 1.0f : 0.0f) : F[i];
     for (int it = 0; it < 16; ++it) {
@@ -627,9 +710,8 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
         const float c20 = R[1] * R[5] - R[2] * R[4], c21 = R[2] * R[3] - R[0] * R[5],
                     c22 = R[0] * R[4] - R[1] * R[3];
         const float det = R[0] * c00 + R[1] * c01 + R[2] * c02;
-        const bool ok = fabsf(det) > 1e-20f;
         // hardware reciprocal (1 ulp): the iteration absorbs its error
-        const float hid = ok ? 0.5f * __builtin_amdgcn_rcpf(det) : 0.0f;
+        const float hid = 0.5f * __builtin_amdgcn_rcpf(det);
         float Rn[9] = {0.5f * R[0] + hid * c00, 0.5f * R[1] + hid * c01, 0.5f * R[2] + hid * c02,
                        0.5f * R[3] + hid * c10, 0.5f * R[4] + hid * c11, 0.5f * R[5] + hid * c12,
                        0.5f * R[6] + hid * c20, 0.5f * R[7] + hid * c21, 0.5f * R[8] + hid * c22};
@@ -638,7 +720,7 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
         for (int i = 0; i < 9; ++i) {
             const float d = Rn[i] - R[i];
             d2 += d * d;
-            R[i] = ok ? Rn[i] : ((i % 4 == 0) ? 1.0f : 0.0f);
+            R[i] = Rn[i];
         }
         // Newton's polar iteration converges quadratically: the error of the
         // new iterate is about |R_new - R|^2 / (2 sigma_min), below 1e-8 once

@@ -49,6 +49,19 @@ __device__ __forceinline__ unsigned long long fixp(double w, double xs) {
     return (unsigned long long)__double_as_longlong(fma(w, xs, FIX_MAGIC)) - FIX_MAGIC_BITS;
 }
 
+// Raw fixed-point term of the LDS node tile: the bits of fma(w, x, 1.5 2^52),
+// FIX_MAGIC_BITS + round(w x 2^32) for |w x| < 2^51, added without removing
+// the offset.  A tile node that received n terms holds n FIX_MAGIC_BITS + S
+// (mod 2^64) in each of its four sums.  FIX_MAGIC_BITS = 2151 * 2^51, so
+// n FIX_MAGIC_BITS mod 2^64 lies in the top 13 bits only; the mass sum S_m
+// of at most 4096 terms (a work item) of at most 2^32 stays below 2^51, so
+// the top 13 bits of the raw mass word are exactly that offset (tile_flush
+// subtracts it from all four sums).
+__device__ __forceinline__ unsigned long long fixr(double w, double xs) {
+    return (unsigned long long)__double_as_longlong(fma(w, xs, FIX_MAGIC));
+}
+constexpr unsigned long long RAW_OFFSET_MASK = 0xFFF8000000000000ull;  // top 13 bits
+
 // P2G straight into the grid buffer, for a particle whose stencil left its tile.
 template <int DIM>
 __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, const double (*w)[3],
@@ -82,7 +95,8 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
 // per unit particle mass, w_i (v + (A/m)(x_i - x_p)) and w_i, accumulated as
 // exact 64-bit fixed point (LDS integer atomics: float LDS atomics are an
 // order of magnitude slower on this part, and integer sums are
-// order-independent).
+// order-independent).  The tile takes raw terms (fixr); the offset comes
+// off at the flush.
 // ---------------------------------------------------------------------------
 template <int DIM, int MAT>
 __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
@@ -191,8 +205,8 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                         const double wt = wzy * w[0][ox];
                         const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
-                        atomicAdd(&acc[3 * TN + idx], fixp(w[0][ox], m32));
+                        for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TN + idx], fixr(wt, val[a]));
+                        atomicAdd(&acc[3 * TN + idx], fixr(w[0][ox], m32));
                     }
                 }
             }
@@ -213,8 +227,8 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                     const double wt = w[1][oy] * w[0][ox];
                     const int idx = l0 + oy * TB + ox;
 #pragma unroll
-                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixp(wt, val[a]));
-                    atomicAdd(&acc[3 * TN + idx], fixp(w[0][ox], m32));
+                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixr(wt, val[a]));
+                    atomicAdd(&acc[3 * TN + idx], fixr(w[0][ox], m32));
                 }
             }
         }
@@ -253,7 +267,8 @@ __device__ __forceinline__ bool tile_node(int t, const int *origin, int res, int
     return ok;
 }
 
-// Adds the tile's non-zero node sums to the grid with int64 atomics and flags
+// Adds the tile's non-zero node sums (raw sums less the offset of their
+// terms, see fixr) to the grid with int64 atomics and flags
 // the node blocks that received data.  A tile (origin = block corner - 1)
 // overlaps 3 node blocks per axis: its first node layer lies in the block
 // before, the next BLK in its own block, the rest in the block after.  The
@@ -298,7 +313,9 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
     // covers whole cache lines (16 nodes) instead of 64 scattered words
     for (int q = threadIdx.x; q < 4 * TN; q += PWG) {
         const int t = q >> 2, c = q & 3;
-        const unsigned long long sum = acc[c * TN + t];
+        const unsigned long long raw = acc[c * TN + t];
+        if (raw == 0ull) continue;  // no terms (a node with terms has a non-zero offset)
+        const unsigned long long sum = raw - (acc[3 * TN + t] & RAW_OFFSET_MASK);
         if (sum != 0ull) {
             if (table) {
                 const uint32_t id = table[t];
@@ -537,14 +554,31 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
         if (do_p2g)
             for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
         __syncthreads();
+#ifdef MPMQ_SCHEME_CONST
+        // the rows of x and of slot 3 (the only fields read from the old
+        // state) of the next particle are loaded while this one is computed
+        constexpr uint32_t RM = field_rows(kSchemeConst.f[0], DIM) | field_rows(kSchemeConst.f[3], nc3<DIM, MAT>());
+        uint32_t rec[MAX_WORDS], nrec[MAX_WORDS];
+        if (it.p0 + (int)threadIdx.x < it.p1) load_rows<RM>(words, cap, (uint32_t)(it.p0 + threadIdx.x) * 4u, nrec);
+#endif
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += PWG) {
             SchemeRef sp = scheme_ref(sch);
             const uint32_t p4 = (uint32_t)p * 4u;
             constexpr int N3 = nc3<DIM, MAT>();
             double xd[DIM];
             float F[N3];
+#ifdef MPMQ_SCHEME_CONST
+            // (every rec row is a register copy, so decoding waits for no load)
+#pragma unroll
+            for (int k = 0; k < MAX_WORDS; ++k)
+                if (RM & (1u << k)) rec[k] = nrec[k];
+            if (p + PWG < it.p1) load_rows<RM>(words, cap, p4 + 4u * PWG, nrec);
+            dec_field_src<DIM, 0, double>(&sp->f[0], RegRows{rec}, xd);
+            dec_field_src<DIM, fid3<MAT>(), float>(&sp->f[3], RegRows{rec}, F);
+#else
             dec_field<DIM, 0, double>(&sp->f[0], words, cap, p4, xd);
             dec_field<DIM, fid3<MAT>(), float>(&sp->f[3], words, cap, p4, F);
+#endif
             int base[DIM];
             float fx[DIM], wx[DIM][3];
             stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
