@@ -14,6 +14,8 @@ Prints one JSON line on stdout; progress goes to stderr.
   python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--config c3|c2|c1]
                   [--no-fp32] [--no-cpu] [--only quant|fp32]
   python bench.py --calib-copy   # plain copy of known size (counter calibration)
+  python bench.py --calib-atomics  # 64-bit global atomic throughput (the flush's peak)
+  python bench.py --config c4 [--batch-streams 4] [--max-particles N]   # serving stream
 """
 from __future__ import annotations
 
@@ -210,11 +212,52 @@ def roofline(res, n, steps):
             "active_nodes_per_step": active}
 
 
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable, os.cpu_count() or 1
+
+
+def _oracle_cube_rate(args):
+    """One worker of the parallel baseline: cube `i` of the 3e8-particle
+    workload through the unchanged oracle, one warm-up substep (with the
+    sort) and `reps` timed substeps.  Returns (particles, seconds)."""
+    i, reps = args
+    import oracle
+    import workloads as WL
+    sub = WL.c3(only=[i])
+    x, v, C, F = sub["state"]
+    words, _ = oracle.encode(sub["scheme"], x, v, C, F, 0, 2)
+    sim = oracle.Sim(sub["scheme"], sub["params"], words)
+    sim.step(1)
+    t0 = time.perf_counter()
+    sim.step(reps)
+    dt = time.perf_counter() - t0
+    sim.close()
+    return sub["n"] * reps, dt
+
+
 def cpu_baseline(scene):
-    """The oracle (FP64, single thread) on a bounded sample of the workload."""
+    """The oracle (FP64) on a bounded sample of the workload: one thread
+    (median of three timed substeps after a warm-up substep) and, for the
+    3e8-particle workload, independent cubes in concurrent processes, one
+    per usable core (at most 16), unchanged oracle code."""
     import numpy as np
     import oracle
     import workloads as WL
+    model, usable, logical = host_cpu()
     if scene["name"] == "c3":
         sub = WL.c3(only=[0])
         sample = (f"cube 0 of 186 ({sub['n']} particles) on the full 512^3 grid, 3 substeps after a "
@@ -239,13 +282,61 @@ def cpu_baseline(scene):
     words, _ = oracle.encode(sub["scheme"], x, v, C, F, 0, 2)
     sim = oracle.Sim(sub["scheme"], sub["params"], words)
     sim.step(1)
-    reps = 3
-    t0 = time.perf_counter()
-    sim.step(reps)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        sim.step(1)
+        times.append(time.perf_counter() - t0)
     sim.close()
-    return {"value": reps * sub["n"] / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": sample, "seconds": round(dt, 3)}
+    med = float(np.median(times))
+    single = sub["n"] / med
+    out = {"value": single, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+           "sample": sample + " (median of three timed substeps)", "seconds": round(sum(times), 3),
+           "host_cpu": model, "usable_cores": usable, "logical_cpus": logical,
+           "single_thread": {"value": round(single, 1), "substep_s": [round(t, 3) for t in times]}}
+    if scene["name"] == "c3" and usable > 1:
+        import multiprocessing as mp
+        procs = min(usable, 16)
+        reps = 2
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(procs) as pool:
+            res = pool.map(_oracle_cube_rate, [(i, reps) for i in range(procs)])
+        wall = time.perf_counter() - t0
+        work = sum(r[0] for r in res)
+        slowest = max(r[1] for r in res)
+        out.update(value=work / slowest, cores=procs,
+                   sample=(f"cubes 0-{procs - 1} of 186 ({work // reps} particles), one per process on "
+                           f"{procs} cores, each on the full 512^3 grid: {reps} timed substeps after a warm-up "
+                           "substep (with the sort); rate = particle-substeps / the slowest process's timed "
+                           f"seconds; single-thread figure: {sample}"),
+                   parallel={"processes": procs, "timed_s": [round(r[1], 3) for r in res],
+                             "wall_s_incl_setup": round(wall, 2)})
+    return out
+
+
+def atomics_peak(mq):
+    """Device-wide 64-bit global atomic adds per second of the library's
+    calibration kernel (mpmq_calib_atomics, stride 1: each wave instruction
+    covers 64 consecutive words) over 2^27 words."""
+    import torch
+    n = 1 << 27
+    buf = torch.zeros(n, dtype=torch.int64, device="cuda")
+    st = torch.cuda.current_stream()
+    mq.calib_atomics(buf, passes=1, stream=st)
+    torch.cuda.synchronize()
+    passes = 4
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    mq.calib_atomics(buf, passes=passes, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ok = bool(torch.all(buf == passes + 1).item())
+    del buf
+    torch.cuda.empty_cache()
+    return {"peak_per_s": n * passes / (ms / 1e3), "words": n, "passes": passes, "ms": round(ms, 3),
+            "pattern": "stride 1 (64 consecutive 8-byte words per wave instruction)", "checked": ok}
 
 
 def calib_copy():
@@ -265,25 +356,37 @@ def bench_serving(a):
     import workloads as WL
     from paper_2207_04658_amd.serving import Server
     t0 = time.time()
-    scenes = [WL.c4_scene(0, i, materialize=False) for i in range(a.scenes)]
+    scenes = [WL.c4_scene(0, i, materialize=False, n_max=a.max_particles) for i in range(a.scenes)]
     arrivals = WL.c4_arrivals(0, a.scenes, a.rate)
     log(f"generated {a.scenes} scenes ({sum(s['n'] for s in scenes)} particles) in {time.time() - t0:.1f}s")
-    warm = Server(streams=2, steps_per_tick=10).run(scenes[:2])  # loads the kernels
+    for batched in (True, False):  # loads the kernels of both paths
+        warm = Server(streams=2, steps_per_tick=10, batched=batched).run(scenes[:2])
     log(f"warm-up: {len(warm.latencies_s)} scenes")
-    res = Server(hbm_budget_bytes=200e9, streams=8, steps_per_tick=10).run(scenes, arrivals)
+    # per-scene launches on 8 streams, for comparison
+    per = Server(hbm_budget_bytes=200e9, streams=8, steps_per_tick=10, batched=False).run(scenes, arrivals)
+    lat_per = np.array(list(per.latencies_s.values()))
+    log(f"per-scene launches: {per.throughput():.3e} particle-substeps/s, p50 {np.percentile(lat_per, 50):.3f} s")
+    res = Server(hbm_budget_bytes=200e9, streams=a.batch_streams, steps_per_tick=10, batched=True).run(scenes, arrivals)
     lat = np.array(list(res.latencies_s.values()))
+    log(f"batched launches: {res.throughput():.3e} particle-substeps/s, p50 {np.percentile(lat, 50):.3f} s")
     line = {
         "metric": "serving throughput (particle-substeps/s) with per-scene latency",
         "value": round(res.throughput(), 1), "unit": "particle-substeps/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{a.scenes} MLS-MPM scenes (2D/3D), Poisson arrivals at {a.rate}/s, "
-                               "particles log-uniform 4096-2^21, grids 32-256 per axis, 100 steps each, "
-                               "random 12-24-bit schemes, 200 GB HBM budget"},
+                               f"particles log-uniform 4096-{a.max_particles}, grids 32-256 per axis, 100 steps "
+                               "each, random 12-24-bit schemes, 200 GB HBM budget"},
         "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
                       "max": round(float(lat.max()), 4)},
         "makespan_s": round(res.makespan_s, 4), "particle_substeps": res.particle_substeps,
         "max_active_scenes": res.max_active, "peak_hbm_bytes": res.peak_bytes,
         "queue_wait_s_max": round(max(res.queue_wait_s.values()), 4),
+        "launches": "batched: one grid-update and one fused-substep launch per substep for all active scenes "
+                    f"of a stream and dimension (mpmq_step_batch), scenes spread over {a.batch_streams} streams",
+        "per_scene_launches": {"value": round(per.throughput(), 1),
+                               "latency_s": {"p50": round(float(np.percentile(lat_per, 50)), 4),
+                                             "p99": round(float(np.percentile(lat_per, 99)), 4)},
+                               "makespan_s": round(per.makespan_s, 4), "streams": 8},
     }
     print(json.dumps(line), flush=True)
 
@@ -350,11 +453,17 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "fluid"])
     ap.add_argument("--scenes", type=int, default=256, help="c4: scenes in the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="c4: Poisson arrival rate (scenes/s)")
+    ap.add_argument("--batch-streams", type=int, default=4, help="c4: streams of the batched server")
+    ap.add_argument("--max-particles", type=int, default=2 ** 21, help="c4: largest scene (log-uniform from 4096)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["quant", "fp32"], default=None)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--calib-atomics", action="store_true",
+                    help="64-bit global atomic adds per second of the calibration kernel")
     ap.add_argument("--generic", action="store_true", help="run the generic (run-time scheme) kernels")
+    ap.add_argument("--sort-every", type=int, default=None,
+                    help="c3: re-sort every S substeps (default: the workload's set-up sort only)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the library has no multi-GPU path (it would shard the grid "
@@ -363,6 +472,11 @@ def main():
         sys.exit(2)
     if a.calib_copy:
         calib_copy()
+        return
+    if a.calib_atomics:
+        import paper_2207_04658_amd as mq
+        mq.load()
+        print(json.dumps({"calib_atomics": atomics_peak(mq)}))
         return
     import torch
     import paper_2207_04658_amd as mq
@@ -375,6 +489,9 @@ def main():
     if a.config == "c5":
         return bench_adjoint(a)
     scene, state = build_scene(a.config, dev)
+    if a.sort_every is not None:
+        scene["params"] = dict(scene["params"], sort_every=int(a.sort_every))
+        scene["desc"] += f"; re-sorted every {a.sort_every} substeps"
     n = scene["n"]
     log(f"scene {scene['name']}: {n} particles")
     out = {}
@@ -401,6 +518,16 @@ def main():
             rf["valu_issue"] = {"achieved": round(ach / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
                                 "unit": "T lane-instr/s", "frac": round(ach / VALU_PEAK_LANE_OPS, 4),
                                 "instructions_per_launch": valu}
+    if rf is not None:
+        # the P2G tile flushes' 64-bit global atomics (counted by the kernel)
+        # against the calibration kernel's rate
+        peak = atomics_peak(mq)
+        per_launch = main_res["stats"].get("atomics", 0) / max(a.steps, 1)
+        ach = per_launch / (rf["avg_launch_ms"] / 1e3)
+        rf["atomics"] = {"achieved": round(ach / 1e9, 3), "peak": round(peak["peak_per_s"] / 1e9, 3),
+                         "unit": "G atomic adds/s", "frac": round(ach / peak["peak_per_s"], 4),
+                         "per_launch": per_launch, "calibration": peak}
+        log(f"atomics: {per_launch:.3e} per launch, {ach:.3e}/s against {peak['peak_per_s']:.3e}/s")
     cpu = None
     if not a.no_cpu:
         log("cpu baseline (oracle) ...")

@@ -146,6 +146,8 @@ typedef struct {
     int64_t clamped;   /* particle scatters (P2G) with a velocity term v - (A/m) f dx or
                           (A/m) dx above 2^12 in magnitude, clamped so that the 64-bit
                           fixed-point node sums cannot overflow (the clamp loses momentum) */
+    int64_t atomics;   /* 64-bit global atomic adds issued by the P2G tile flushes (the
+                          scatter of each work item's node sums into the grid) */
 } mpmq_stats_t;
 
 typedef struct mpmq_ctx mpmq_ctx;
@@ -188,6 +190,20 @@ mpmq_status mpmq_packed(mpmq_ctx *ctx, const uint32_t **words, int32_t *W, int64
  * Asynchronous.  ESTATE before the first encode. */
 mpmq_status mpmq_step(mpmq_ctx *ctx, int32_t n_substeps);
 
+/* Batched substeps for serving many scenes: advances every context of
+ * ctxs[0..count) by n_substeps, each exactly as mpmq_step would (same
+ * results bit for bit: each scene keeps its own scheme, parameters, buffers,
+ * step counter and Philox key), but with the grid update and the fused
+ * substep of all scenes issued as one launch each per substep (per chunk of
+ * up to 96 scenes; sorts and the P2G after a sort stay per scene).  The
+ * contexts must share the dimension, the material and the stream (the
+ * launches go to that stream), and each may appear once.  Scheme-specialized
+ * kernels (mpmq_specialize) are not used here.  Asynchronous.  EINVAL (NULL,
+ * count < 1, mixed dimension / material / stream, duplicates), ESTATE
+ * (a context before its first encode), EDEVICE; the message of any error is
+ * mpmq_last_error(ctxs[0]) (of mpmq_last_error(NULL) when ctxs[0] is NULL). */
+mpmq_status mpmq_step_batch(mpmq_ctx *const *ctxs, int32_t count, int32_t n_substeps);
+
 /* Substep counter (the Philox "step" of the next substep). */
 mpmq_status mpmq_step_count(mpmq_ctx *ctx, int64_t *out);
 
@@ -212,6 +228,13 @@ mpmq_status mpmq_set_stats(mpmq_ctx *ctx, int32_t level);
 /* Accumulated statistics.  Synchronizes the stream. */
 mpmq_status mpmq_stats(mpmq_ctx *ctx, mpmq_stats_t *out);
 mpmq_status mpmq_reset_stats(mpmq_ctx *ctx);
+
+/* Calibration aid for the measurement of the P2G flush: adds 1 to word
+ * (i * stride) mod n_words of buf for every i < n_words, `passes` times, with
+ * 64-bit global atomics (stride 1: each wave instruction covers 64
+ * consecutive words), on hip_stream.  buf: device, 256-byte aligned, owned by
+ * the caller.  Asynchronous.  EINVAL on bad arguments. */
+mpmq_status mpmq_calib_atomics(uint64_t *buf, int64_t n_words, int32_t passes, int64_t stride, void *hip_stream);
 
 /* Per-kernel timing with HIP events recorded on the context stream around
  * every launch while enabled.  mpmq_kernel_times synchronizes and returns,

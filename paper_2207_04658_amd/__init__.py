@@ -73,7 +73,8 @@ class mpmq_buffers(ct.Structure):
 class mpmq_stats_t(ct.Structure):
     _fields_ = [("sat", ct.c_int64 * 4), ("nan", ct.c_int64 * 4), ("up", ct.c_int64 * 4),
                 ("down", ct.c_int64 * 4), ("steps", ct.c_int64), ("sorts", ct.c_int64),
-                ("fallback", ct.c_int64), ("active_nodes", ct.c_int64), ("clamped", ct.c_int64)]
+                ("fallback", ct.c_int64), ("active_nodes", ct.c_int64), ("clamped", ct.c_int64),
+                ("atomics", ct.c_int64)]
 
 
 class mpmq_kernel_time(ct.Structure):
@@ -122,6 +123,10 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2207_04658_amd/build.py "
                           "(or __graft_entry__.build()); there is no CPU fallback")
+    # torch first: the library then binds the HIP runtime torch loaded (one
+    # runtime per process, so torch's device buffers and streams are valid
+    # handles for the library)
+    import torch  # noqa: F401
     L = ct.CDLL(path)
     P = ct.c_void_p
     S = ct.c_int
@@ -134,6 +139,8 @@ def load(path: str = LIB_PATH):
         "mpmq_decode": [P, P, P, P, P],
         "mpmq_packed": [P, ct.POINTER(P), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)],
         "mpmq_step": [P, ct.c_int32],
+        "mpmq_step_batch": [ct.POINTER(P), ct.c_int32, ct.c_int32],
+        "mpmq_calib_atomics": [P, ct.c_int64, ct.c_int32, ct.c_int64, P],
         "mpmq_step_count": [P, ct.POINTER(ct.c_int64)],
         "mpmq_stats": [P, ct.POINTER(mpmq_stats_t)],
         "mpmq_reset_stats": [P],
@@ -164,7 +171,7 @@ def load(path: str = LIB_PATH):
 
 def exported_symbols():
     return ["mpmq_query_sizes", "mpmq_create", "mpmq_destroy", "mpmq_encode", "mpmq_decode",
-            "mpmq_packed", "mpmq_step", "mpmq_step_count", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
+            "mpmq_packed", "mpmq_step", "mpmq_step_batch", "mpmq_step_count", "mpmq_calib_atomics", "mpmq_stats", "mpmq_reset_stats", "mpmq_set_stats",
             "mpmq_specialize",
             "mpmq_set_timing", "mpmq_kernel_times", "mpmq_adjoint_workspace", "mpmq_adjoint", "mpmq_adjoint_static", "mpmq_solve_scheme", "mpmq_auto_scheme", "mpmq_solver_error", "mpmq_error_string",
             "mpmq_last_error"]
@@ -323,7 +330,7 @@ class Context:
         out = {names[i]: {"sat": st.sat[i], "nan": st.nan[i], "up": st.up[i], "down": st.down[i]}
                for i in range(4)}
         out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes,
-                   clamped=st.clamped)
+                   clamped=st.clamped, atomics=st.atomics)
         return out
 
     def set_stats(self, level):
@@ -412,6 +419,29 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def calib_atomics(buf, passes=1, stride=1, stream=None):
+    """mpmq_calib_atomics on a uint64/int64 CUDA tensor (see include/mpmq.h)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(buf.device)
+    s = load().mpmq_calib_atomics(ct.c_void_p(buf.data_ptr()), int(buf.numel()), int(passes), int(stride),
+                                  ct.c_void_p(st.cuda_stream))
+    if s != 0:
+        raise MpmqError(s, load().mpmq_last_error(None).decode())
+
+
+def step_batch(contexts, n_substeps=1):
+    """mpmq_step_batch: advances every Context of `contexts` (same dimension,
+    material and stream) by n_substeps with one launch per kernel for the
+    whole batch."""
+    ctxs = list(contexts)
+    if not ctxs:
+        return
+    arr = (ct.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+    st = load().mpmq_step_batch(arr, len(ctxs), int(n_substeps))
+    if st != 0:
+        raise MpmqError(st, load().mpmq_last_error(ctxs[0]._h).decode())
 
 
 def solve_scheme(P, g, R, mode="error", eps=1e-3, z=1.0, min_bits=1, max_bits=32):

@@ -376,18 +376,19 @@ __global__ __launch_bounds__(WG) void k_items(const uint32_t *__restrict__ cell_
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double from_fix(unsigned long long v) { return (double)(long long)v; }
 
-// Persistent: work-group g walks node blocks g, g + gridDim.x, ...; a block
-// flagged in fcur gets its fixed-point sums turned into float4 (v, m) in
-// place, a block flagged in fnxt is cleared for the next P2G.  One count
-// atomic per work-group.
+// Persistent: work-group g of ngroups walks node blocks g, g + ngroups, ...;
+// a block flagged in fcur gets its fixed-point sums turned into float4
+// (v, m) in place, a block flagged in fnxt is cleared for the next P2G.  One
+// count atomic per work-group.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restrict__ gcur,
-                                                    GNode *__restrict__ gnxt, uint32_t *__restrict__ fcur,
-                                                    uint32_t *__restrict__ fnxt, int64_t nblocks, uint64_t *stats) {
+__device__ __forceinline__ void grid_update_blocks(const DevParams &P, GNode *__restrict__ gcur,
+                                                   GNode *__restrict__ gnxt, uint32_t *__restrict__ fcur,
+                                                   uint32_t *__restrict__ fnxt, int64_t nblocks, uint64_t *stats,
+                                                   uint32_t g, uint32_t ngroups) {
     constexpr int B = Geo<DIM>::BLK, CPB = Geo<DIM>::CPB, L = Geo<DIM>::LOG;
     static_assert(CPB % WG == 0, "a node block is a whole number of work-group passes");
     uint32_t active = 0;
-    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    for (int64_t b = g; b < nblocks; b += ngroups) {
         const bool tc = fcur[b] != 0u, tn = fnxt[b] != 0u;
         // every wave has read fnxt[b] before thread 0 resets it below (the
         // waves of a group do not run in lockstep)
@@ -452,9 +453,27 @@ __global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restri
 #pragma unroll
         for (int i = 0; i < WG / 64; ++i) tot += wsum[i];
         if (tot)
-            atomicAdd((unsigned long long *)&stats[ST_ACTIVE + (blockIdx.x % ST_ACTIVE_SLOTS)],
-                      (unsigned long long)tot);
+            atomicAdd((unsigned long long *)&stats[ST_ACTIVE + (g % ST_ACTIVE_SLOTS)], (unsigned long long)tot);
     }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_grid_update(DevParams P, GNode *__restrict__ gcur,
+                                                    GNode *__restrict__ gnxt, uint32_t *__restrict__ fcur,
+                                                    uint32_t *__restrict__ fnxt, int64_t nblocks, uint64_t *stats) {
+    grid_update_blocks<DIM>(P, gcur, gnxt, fcur, fnxt, nblocks, stats, blockIdx.x, gridDim.x);
+}
+
+// Batched grid update: work-group g serves the scene whose group range holds
+// it (see k_substep_batch), with that scene's grids for its step.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_grid_update_batch(const BatchArgs args) {
+    const int i = batch_scene(args, blockIdx.x);
+    const BatchRef d = batch_ref(args.desc[i]);
+    const DevParams P = batch_params(d);
+    const uint32_t g0 = args.group_begin[i], cur = args.step[i] & 1u;
+    grid_update_blocks<DIM>(P, d->grid[cur], d->grid[cur ^ 1u], d->flags[cur], d->flags[cur ^ 1u], d->nblocks,
+                            d->stats, blockIdx.x - g0, args.group_begin[i + 1] - g0);
 }
 
 template <int DIM>
@@ -471,6 +490,17 @@ __global__ __launch_bounds__(WG) void k_clear_touched(GNode *__restrict__ g, uin
         reinterpret_cast<ulonglong4 *>(g + (b << (DIM * L)) + l)[0] = z;
     }
     if (threadIdx.x == 0) flags[b] = 0u;
+}
+
+// Calibration of 64-bit global atomic throughput: every thread adds 1 to
+// word (i * stride) mod n for its indices i, `passes` times (stride 1: each
+// wave instruction covers 64 consecutive words).
+__global__ __launch_bounds__(WG) void k_calib_atomics(unsigned long long *__restrict__ buf, int64_t n, int passes,
+                                                      int64_t stride) {
+    const int64_t nthreads = (int64_t)gridDim.x * WG;
+    for (int r = 0; r < passes; ++r)
+        for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += nthreads)
+            atomicAdd(buf + (i * stride) % n, 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,6 +643,28 @@ hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *g
     else
         hipLaunchKernelGGL(k_grid_update<2>, grid, dim3(WG), 0, st, p, gcur, gnxt, flags_cur, flags_nxt, nblocks,
                            stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_calib_atomics(unsigned long long *buf, int64_t n, int passes, int64_t stride, hipStream_t st) {
+    const dim3 grid((unsigned)std::min<int64_t>((n + WG - 1) / WG, 65536));
+    hipLaunchKernelGGL(k_calib_atomics, grid, dim3(WG), 0, st, buf, n, passes, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_update_batch(int dim, const BatchArgs &a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    const dim3 grid(a.group_begin[a.count]);
+    if (dim == 3) hipLaunchKernelGGL(k_grid_update_batch<3>, grid, dim3(WG), 0, st, a);
+    else hipLaunchKernelGGL(k_grid_update_batch<2>, grid, dim3(WG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_substep_batch(int dim, int mat, int round_stats, const BatchArgs &a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    const dim3 grid(a.group_begin[a.count]);
+    if (round_stats) MPMQ_DISPATCH2(dim, mat, k_substep_batch, true, grid, a);
+    else MPMQ_DISPATCH2(dim, mat, k_substep_batch, false, grid, a);
     return hipGetLastError();
 }
 

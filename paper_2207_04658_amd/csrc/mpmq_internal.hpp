@@ -78,10 +78,11 @@ struct DevParams {
 };
 
 // Statistics slots (uint64) in scratch.  ST_CLAMP: particles whose P2G
-// terms were clamped to the fixed-point range (see p2g_particle).
+// terms were clamped to the fixed-point range (see p2g_particle);
+// ST_ATOMICS: 64-bit global atomic adds issued by the P2G tile flushes.
 enum {
     ST_SAT = 0, ST_NAN = 4, ST_UP = 8, ST_DOWN = 12, ST_FALLBACK = 16, ST_ACTIVE = 17, ST_ACTIVE_SLOTS = 7,
-    ST_CLAMP = 24, ST_COUNT = 25
+    ST_CLAMP = 24, ST_ATOMICS = 25, ST_COUNT = 26
 };
 
 // Device scratch layout (byte offsets, all 256-aligned).
@@ -96,11 +97,35 @@ struct Scratch {
     int64_t stats;                       // ST_COUNT uint64
     int64_t misc;                        // 64 uint32 (n_items, ...)
     int64_t scheme;                      // device copy of the DevScheme
+    int64_t batch;                       // the context's BatchDesc
     int64_t total;
     int64_t ncells, nblocks, max_items, hist_entries, scan_tmp_entries;
 };
 
 struct WorkItem { int32_t block, p0, p1, pad; };
+
+// Batched launches (serving): a context's buffers and parameters, kept in its
+// scratch in device memory, and the per-launch table of scenes.
+struct BatchDesc {
+    const DevScheme *scheme;
+    uint32_t *words;
+    int64_t cap;
+    const WorkItem *items;
+    const uint32_t *n_items;
+    GNode *grid[2];
+    uint32_t *flags[2];
+    uint64_t *stats;
+    int64_t nblocks;
+    DevParams P;
+};
+constexpr int MAX_BATCH = 96;  // scenes per batched launch (the table is a kernel argument)
+struct BatchArgs {
+    int32_t count, pad;
+    uint32_t group_begin[MAX_BATCH + 1];  // first work-group of each scene; [count] = total
+    const BatchDesc *desc[MAX_BATCH];
+    uint32_t step[MAX_BATCH];             // the scene's substep index (Philox step; grid G[step & 1])
+    uint32_t mode[MAX_BATCH];             // bit 0: scatter the stored state (P2G); bit 1: flush encoder counters
+};
 
 #ifndef __HIPCC_RTC__
 // ---- launchers (kernels.hip) ----
@@ -126,6 +151,7 @@ hipError_t launch_items(const uint32_t *cell_start, const uint32_t *block_items_
 hipError_t launch_gather_u32(const uint32_t *in, const uint32_t *perm, uint32_t *out, int64_t n,
                              hipStream_t st);
 hipError_t launch_copy_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t st);
+hipError_t launch_calib_atomics(unsigned long long *buf, int64_t n, int passes, int64_t stride, hipStream_t st);
 // Kernels compiled at run time with a context's scheme as constants
 // (jit.hip); null entries fall back to the generic kernels.
 struct JitKernels {
@@ -144,6 +170,10 @@ hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *g
                               uint32_t *flags_cur, uint32_t *flags_nxt, int64_t nblocks,
                               uint64_t *stats, hipStream_t st);
 hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblocks, hipStream_t st);
+// Batched grid update / fused substep of a.count scenes of one dimension and
+// material (group_begin counts the launch's work-groups per scene).
+hipError_t launch_grid_update_batch(int dim, const BatchArgs &a, hipStream_t st);
+hipError_t launch_substep_batch(int dim, int mat, int round_stats, const BatchArgs &a, hipStream_t st);
 hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams &p, uint32_t *words,
                           int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
                           const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, uint32_t step,

@@ -183,6 +183,7 @@ Scratch plan_scratch(int dim, int res, int64_t cap_pad) {
     s.stats = o; o = align256(o + 8 * ST_COUNT);
     s.misc = o; o = align256(o + 256);
     s.scheme = o; o = align256(o + (int64_t)sizeof(DevScheme));
+    s.batch = o; o = align256(o + (int64_t)sizeof(BatchDesc));
     s.total = o;
     return s;
 }
@@ -211,6 +212,7 @@ struct mpmq_ctx {
     std::string err;
     JitKernels jit{};
     bool use_jit = false;
+    BatchDesc bdesc{};  // host copy of the device descriptor (source of its upload)
 
     const JitKernels *jit_ptr() const { return use_jit ? &jit : nullptr; }
     uint32_t *u32(int64_t off) { return reinterpret_cast<uint32_t *>(scratch + off); }
@@ -219,6 +221,7 @@ struct mpmq_ctx {
     uint32_t *n_items() { return u32(sp.misc); }
     WorkItem *items() { return reinterpret_cast<WorkItem *>(scratch + sp.items); }
     const DevScheme *dscheme() { return reinterpret_cast<const DevScheme *>(scratch + sp.scheme); }
+    const BatchDesc *dbatch() { return reinterpret_cast<const BatchDesc *>(scratch + sp.batch); }
 };
 
 namespace {
@@ -314,14 +317,13 @@ mpmq_status do_sort(mpmq_ctx *c) {
     return MPMQ_OK;
 }
 
-// One substep on c->words: sort when due (allow_sort), P2G unless the
-// previous substep already scattered this state, grid update, fused
-// G2P / update / encode / store / P2G kernel.
-mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
+// First part of a substep: sort when due (allow_sort), and P2G unless the
+// previous substep already scattered this state.
+mpmq_status pre_substep(mpmq_ctx *c, bool allow_sort) {
     hipStream_t st = c->stream;
     const int S = c->params.sort_every;
     const int64_t s = c->step;
-    const int cur = (int)(s & 1), nxt = cur ^ 1;
+    const int cur = (int)(s & 1);
     const bool need_sort = allow_sort && (!c->sorted || (S > 0 && s % S == 0 && c->sorted_at != s));
     if (need_sort) {
         if (c->p2g_ready) {
@@ -339,22 +341,105 @@ mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
         HIPCHK(c, launch_p2g(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                              c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st, c->jit_ptr()), "p2g");
     }
+    return MPMQ_OK;
+}
+
+// Whether the substep after the current one sorts (then the fused kernel
+// does not scatter its stored state).
+bool next_sorts(const mpmq_ctx *c, bool allow_sort) {
+    const int S = c->params.sort_every;
+    return allow_sort && S > 0 && ((c->step + 1) % S) == 0;
+}
+
+// Host state after a substep's launches.
+void post_substep(mpmq_ctx *c, bool allow_sort) {
+    c->p2g_ready = !next_sorts(c, allow_sort);
+    c->step += 1;
+    c->steps_taken += 1;
+}
+
+// One substep on c->words: pre_substep, grid update, fused
+// G2P / update / encode / store / P2G kernel.
+mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
+    mpmq_status r = pre_substep(c, allow_sort);
+    if (r != MPMQ_OK) return r;
+    hipStream_t st = c->stream;
+    const int64_t s = c->step;
+    const int cur = (int)(s & 1), nxt = cur ^ 1;
     {
         Timed t(c, "grid_update");
         HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[cur], c->grid[nxt], c->flags(cur), c->flags(nxt),
                                      c->sp.nblocks, c->stats(), st), "grid update");
     }
-    const bool next_sorts = allow_sort && S > 0 && ((s + 1) % S) == 0;
     {
         Timed t(c, "substep");
         HIPCHK(c, launch_substep(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
                                  c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
-                                 next_sorts ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st, c->jit_ptr()),
+                                 next_sorts(c, allow_sort) ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st,
+                                 c->jit_ptr()),
                "substep");
     }
-    c->p2g_ready = !next_sorts;
-    c->step = s + 1;
-    c->steps_taken += 1;
+    post_substep(c, allow_sort);
+    return MPMQ_OK;
+}
+
+// One substep of every context of a batch (same dimension, material and
+// stream): per-scene sorts and bootstrap P2G, then a batched grid update and
+// a batched fused kernel per chunk of up to MAX_BATCH scenes, grouped by
+// whether the scene counts round-ups / round-downs.
+mpmq_status batch_substep(mpmq_ctx *const *all, int count_all) {
+    // scenes without particles only advance their counters (as mpmq_step)
+    std::vector<mpmq_ctx *> live;
+    for (int i = 0; i < count_all; ++i) {
+        if (all[i]->n > 0) {
+            live.push_back(all[i]);
+        } else {
+            all[i]->step += 1;
+            all[i]->steps_taken += 1;
+        }
+    }
+    if (live.empty()) return MPMQ_OK;
+    mpmq_ctx *const *ctxs = live.data();
+    const int count = (int)live.size();
+    mpmq_ctx *c0 = ctxs[0];
+    hipStream_t st = c0->stream;
+    for (int i = 0; i < count; ++i) {
+        mpmq_status r = pre_substep(ctxs[i], true);
+        if (r != MPMQ_OK) {
+            all[0]->err = ctxs[i]->err;  // batch errors are reported on the first context
+            return r;
+        }
+    }
+    for (int rs = 0; rs < 2; ++rs) {
+        int i = 0;
+        while (i < count) {
+            BatchArgs ga{}, sa{};
+            int k = 0;
+            for (; i < count && k < MAX_BATCH; ++i) {
+                mpmq_ctx *c = ctxs[i];
+                if ((c->stats_level >= 1 ? 1 : 0) != rs) continue;
+                // grid update: the per-scene launch's group count (a multiple of 8)
+                const uint32_t gg = (uint32_t)((std::min<int64_t>(c->sp.nblocks, 4096) + 7) / 8 * 8);
+                ga.desc[k] = sa.desc[k] = c->dbatch();
+                ga.step[k] = sa.step[k] = (uint32_t)c->step;
+                ga.mode[k] = sa.mode[k] = (next_sorts(c, true) ? 0u : 1u) | 2u;
+                ga.group_begin[k + 1] = ga.group_begin[k] + gg;
+                sa.group_begin[k + 1] = sa.group_begin[k] + (uint32_t)c->launch_grid;
+                ++k;
+            }
+            ga.count = sa.count = k;
+            if (k == 0) continue;
+            {
+                Timed t(c0, "grid_update_batch");
+                HIPCHK(c0, launch_grid_update_batch(c0->dim, ga, st), "batch grid update");
+            }
+            {
+                Timed t(c0, "substep_batch");
+                HIPCHK(c0, launch_substep_batch(c0->dim, c0->ds.mat, rs, sa, st), "batch substep");
+            }
+        }
+    }
+    for (int i = 0; i < count; ++i) post_substep(ctxs[i], true);
     return MPMQ_OK;
 }
 
@@ -623,6 +708,20 @@ mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params, co
     if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.stats, 0, 8 * ST_COUNT, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->sp.misc, 0, 256, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->scratch + c->sp.scheme, &c->ds, sizeof(DevScheme), hipMemcpyHostToDevice, c->stream);
+    BatchDesc &bd = c->bdesc;
+    bd.scheme = c->dscheme();
+    bd.words = c->words;
+    bd.cap = c->cap_pad;
+    bd.items = c->items();
+    bd.n_items = c->n_items();
+    bd.grid[0] = c->grid[0];
+    bd.grid[1] = c->grid[1];
+    bd.flags[0] = c->flags(0);
+    bd.flags[1] = c->flags(1);
+    bd.stats = c->stats();
+    bd.nblocks = c->sp.nblocks;
+    bd.P = c->dp;
+    if (e == hipSuccess) e = hipMemcpyAsync(c->scratch + c->sp.batch, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         g_last_error = std::string("create: ") + hipGetErrorString(e);
@@ -691,6 +790,40 @@ mpmq_status mpmq_step(mpmq_ctx *c, int32_t n_substeps) {
     return MPMQ_OK;
 }
 
+mpmq_status mpmq_step_batch(mpmq_ctx *const *ctxs, int32_t count, int32_t n_substeps) {
+    if (!ctxs || count < 1) return fail(nullptr, MPMQ_EINVAL, "ctxs is NULL or count < 1");
+    if (n_substeps < 0) return fail(nullptr, MPMQ_EINVAL, "n_substeps < 0");
+    mpmq_ctx *c0 = ctxs[0];
+    if (!c0) return fail(nullptr, MPMQ_EINVAL, "ctxs[0] is NULL");
+    std::vector<const mpmq_ctx *> seen;
+    for (int i = 0; i < count; ++i) {
+        mpmq_ctx *c = ctxs[i];
+        if (!c) return fail(c0, MPMQ_EINVAL, "ctxs[" + std::to_string(i) + "] is NULL");
+        if (c->dim != c0->dim || c->ds.mat != c0->ds.mat)
+            return fail(c0, MPMQ_EINVAL, "batched contexts must share the dimension and the material");
+        if (c->stream != c0->stream) return fail(c0, MPMQ_EINVAL, "batched contexts must share one stream");
+        if (!c->encoded) return fail(c0, MPMQ_ESTATE, "step before encode (ctxs[" + std::to_string(i) + "])");
+        seen.push_back(c);
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+        return fail(c0, MPMQ_EINVAL, "a context appears twice in the batch");
+    for (int32_t s = 0; s < n_substeps; ++s) {
+        mpmq_status r = batch_substep(ctxs, count);
+        if (r != MPMQ_OK) return r;
+    }
+    return MPMQ_OK;
+}
+
+mpmq_status mpmq_calib_atomics(uint64_t *buf, int64_t n_words, int32_t passes, int64_t stride, void *hip_stream) {
+    if (!buf || n_words < 1 || passes < 1 || stride < 1 || ((uintptr_t)buf & 255u))
+        return fail(nullptr, MPMQ_EINVAL, "calib_atomics: need an aligned buffer, n_words, passes, stride >= 1");
+    const hipError_t e = launch_calib_atomics(reinterpret_cast<unsigned long long *>(buf), n_words, passes, stride,
+                                              (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, MPMQ_EDEVICE, std::string("calib_atomics: ") + hipGetErrorString(e));
+    return MPMQ_OK;
+}
+
 mpmq_status mpmq_step_count(mpmq_ctx *c, int64_t *out) {
     if (!c || !out) return fail(c, MPMQ_EINVAL, "ctx or out is NULL");
     *out = c->step;
@@ -712,6 +845,7 @@ mpmq_status mpmq_stats(mpmq_ctx *c, mpmq_stats_t *out) {
     out->sorts = c->sorts;
     out->fallback = (int64_t)h[ST_FALLBACK];
     out->clamped = (int64_t)h[ST_CLAMP];
+    out->atomics = (int64_t)h[ST_ATOMICS];
     out->active_nodes = 0;
     for (int i = 0; i < ST_ACTIVE_SLOTS; ++i) out->active_nodes += (int64_t)h[ST_ACTIVE + i];
     return MPMQ_OK;

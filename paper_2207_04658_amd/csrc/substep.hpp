@@ -103,7 +103,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                                              const float *C, const float *F, const int *origin,
                                              unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
                                              uint32_t *__restrict__ flags, uint32_t &fallback,
-                                             uint32_t &clamped) {
+                                             uint32_t &clamped, const bool tile_ok = true) {
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
     // |q|, |a_b| <= 2^12 keeps a node value q + sum_b a_b o_b below 2^15
     // (2^47 in fixed point), so a node sum of up to 2^16 contributions stays
@@ -171,7 +171,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
         q[a] = (double)fminf(fmaxf(t, -LIM), LIM) * FIX_ONE;
     }
     clamped += (big > LIM) ? 1u : 0u;
-    bool in_tile = true;
+    bool in_tile = tile_ok;
     int l[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -233,10 +233,16 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
             }
         }
     } else {
-        fallback += 1;
+        fallback += tile_ok ? 1u : 0u;
         p2g_global<DIM>(P, base, w, q, ac, gout, flags);
     }
 }
+
+// Work items with this many particles or fewer skip the node tiles: their
+// particles gather and scatter straight from and to the grid buffers (a
+// sparse scene gives items of a few particles, for which loading and
+// flushing a whole tile costs more than the particles' own global accesses).
+template <int DIM> constexpr int sparse_item() { return Geo<DIM>::TN / 48; }
 
 // tile helpers ---------------------------------------------------------------
 template <int DIM>
@@ -291,10 +297,11 @@ __device__ __forceinline__ int tile_block_code(const int *ijk, const int *origin
 // `table` (optional LDS scratch of TN words + TN bytes, free at the flush):
 // the grid index and block code of every tile node are computed once, not
 // once per component.
+// natom counts the lane's global atomic adds.
 template <int DIM>
 __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin,
                                            const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
-                                           uint32_t *__restrict__ flags, uint32_t *touched,
+                                           uint32_t *__restrict__ flags, uint32_t *touched, uint32_t &natom,
                                            uint32_t *__restrict__ table = nullptr) {
     constexpr int TN = Geo<DIM>::TN, TB = Geo<DIM>::TB, B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
     unsigned char *code = reinterpret_cast<unsigned char *>(table + TN);
@@ -321,11 +328,13 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
                 const uint32_t id = table[t];
                 if (id == 0xffffffffu) continue;  // never reached: contributions stay in-grid
                 atomicAdd(gout[id].q + c, sum);
+                ++natom;
                 touched[code[t]] = 1u;
             } else {
                 int ijk[DIM];
                 if (!tile_node<DIM>(t, origin, P.res, ijk)) continue;  // never reached, as above
                 atomicAdd(gout[node_index<DIM>(ijk, P.nb)].q + c, sum);
+                ++natom;
                 touched[tile_block_code<DIM>(ijk, origin)] = 1u;
             }
         }
@@ -351,6 +360,35 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
     }
 }
 
+// A context's batch descriptor is never written by a kernel: read through
+// the constant address space it stays in scalar registers.
+typedef const __attribute__((address_space(4))) BatchDesc *BatchRef;
+__device__ __forceinline__ BatchRef batch_ref(const BatchDesc *p) { return (BatchRef)p; }
+// The simulation parameters of a descriptor, word by word (scalar loads).
+__device__ __forceinline__ DevParams batch_params(BatchRef d) {
+    static_assert(sizeof(DevParams) % 4 == 0, "DevParams is a whole number of words");
+    typedef const __attribute__((address_space(4))) uint32_t *WordRef;
+    const WordRef src = (WordRef)&d->P;
+    uint32_t w[sizeof(DevParams) / 4];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(DevParams) / 4); ++k) w[k] = src[k];
+    DevParams out;
+    __builtin_memcpy(&out, w, sizeof(DevParams));
+    return out;
+}
+
+// Scene of work-group g in a batched launch (binary search over the
+// scenes' first work-groups; the arguments are wave-uniform).
+__device__ __forceinline__ int batch_scene(const BatchArgs &a, uint32_t g) {
+    int lo = 0, hi = a.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.group_begin[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Work-item walk (a group takes one item or several, depending on the grid
 // size).  Work-groups are dispatched round-robin over the
@@ -361,10 +399,13 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
 // ---------------------------------------------------------------------------
 struct ItemWalk {
     uint32_t first, stride, end;
-    __device__ ItemWalk(uint32_t nit) {
-        const uint32_t x = blockIdx.x & 7u, per = gridDim.x >> 3;
+    __device__ ItemWalk(uint32_t nit) : ItemWalk(nit, blockIdx.x, gridDim.x) {}
+    // group `bid` of `ngroups` (a multiple of 8, starting at a multiple of 8
+    // of the launch, so that bid & 7 is still the XCD)
+    __device__ ItemWalk(uint32_t nit, uint32_t bid, uint32_t ngroups) {
+        const uint32_t x = bid & 7u, per = ngroups >> 3;
         const uint32_t chunk = (nit + 7u) >> 3;
-        first = x * chunk + (blockIdx.x >> 3);
+        first = x * chunk + (bid >> 3);
         stride = per;
         end = min(nit, (x + 1u) * chunk);
     }
@@ -385,26 +426,29 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
     __shared__ uint32_t touched[27];
     if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const uint32_t nit = *n_items;
-    uint32_t fallback = 0, clamped = 0;
+    uint32_t fallback = 0, clamped = 0, natom = 0;
     const ItemWalk walk(nit);
     for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
         const WorkItem it = items[item];
+        const bool tiled = it.p1 - it.p0 > sparse_item<DIM>();  // uniform over the group
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
-        for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
+        if (tiled)
+            for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
         __syncthreads();
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += PWG) {
             double xd[DIM];
             float v[DIM], C[D2], F[nc3<DIM, MAT>()];
             decode_all<DIM, float, MAT>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
-            p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback, clamped);
+            p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback, clamped, tiled);
         }
         __syncthreads();
-        tile_flush<DIM>(P, origin, acc, gout, flags, touched);
+        if (tiled) tile_flush<DIM>(P, origin, acc, gout, flags, touched, natom);
     }
     add_stat(stats, ST_FALLBACK, fallback);
     add_stat(stats, ST_CLAMP, clamped);
+    add_stat(stats, ST_ATOMICS, natom);
 }
 
 
@@ -518,41 +562,40 @@ __device__ __forceinline__ void g2p_global(const GNode *__restrict__ gcur, int n
     }
 }
 
+// The work items of one scene that a work-group takes (walk), each: the
+// velocity tile from gcur, G2P, update, dithered encode and store in place,
+// P2G of the stored state into the LDS accumulator tile, and its flush to
+// gnxt.  gv / acc / touched: the group's LDS tiles (touched zero on entry).
 template <int DIM, bool RS, int MAT>
-__global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevScheme *__restrict__ sch, DevParams Parg, uint32_t *words,
-                                                int64_t cap_arg, const WorkItem *__restrict__ items,
-                                                const uint32_t *__restrict__ n_items,
-                                                const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
-                                                uint32_t *__restrict__ flags, uint32_t step, int do_p2g,
-                                                int collect_stats, uint64_t *stats) {
-    const DevParams &P = params_ref(Parg);
-    const int64_t cap = cap_ref(cap_arg);
+__device__ __forceinline__ void substep_items(const DevScheme *__restrict__ sch, const DevParams &P, uint32_t *words,
+                                              const int64_t cap, const WorkItem *__restrict__ items,
+                                              const ItemWalk &walk, const GNode *__restrict__ gcur,
+                                              GNode *__restrict__ gnxt, uint32_t *__restrict__ flags, uint32_t step,
+                                              int do_p2g, int collect_stats, uint64_t *stats, float *gv,
+                                              unsigned long long *acc, uint32_t *touched) {
     constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
-    __shared__ float gv[DIM * TN];
-    __shared__ unsigned long long acc[4 * TN];
-    __shared__ uint32_t touched[27];
-    if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
-    const uint32_t nit = *n_items;
-    uint32_t fallback = 0, clamped = 0;
+    uint32_t fallback = 0, clamped = 0, natom = 0;
     LaneStats ls;
     ls.clear();
-    const ItemWalk walk(nit);
     for (uint32_t item = walk.first; item < walk.end; item += walk.stride) {
         const WorkItem it = items[item];
+        const bool tiled = it.p1 - it.p0 > sparse_item<DIM>();  // uniform over the group
         int origin[DIM];
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
-        for (int t = threadIdx.x; t < TN; t += PWG) {
-            int ijk[DIM];
-            float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (tile_node<DIM>(t, origin, P.res, ijk))
-                g = node_vel<DIM>(gcur, node_index<DIM>(ijk, P.nb));
-            gv[t] = g.x;
-            gv[TN + t] = g.y;
-            if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
+        if (tiled) {
+            for (int t = threadIdx.x; t < TN; t += PWG) {
+                int ijk[DIM];
+                float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (tile_node<DIM>(t, origin, P.res, ijk))
+                    g = node_vel<DIM>(gcur, node_index<DIM>(ijk, P.nb));
+                gv[t] = g.x;
+                gv[TN + t] = g.y;
+                if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
+            }
+            if (do_p2g)
+                for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
         }
-        if (do_p2g)
-            for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
         __syncthreads();
 #ifdef MPMQ_SCHEME_CONST
         // the rows of x and of slot 3 (the only fields read from the old
@@ -582,7 +625,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             int base[DIM];
             float fx[DIM], wx[DIM][3];
             stencil_base<DIM>(xd, P.inv_dx_d, P.res, base, fx);
-            bool in_tile = true;
+            bool in_tile = tiled;
             int l[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -601,7 +644,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
                 const int l0 = (DIM == 3) ? (l[DIM - 1] * TB + l[1]) * TB + l[0] : l[1] * TB + l[0];
                 g2p_tile<DIM>(gv, l0, wx, fx, nv, S);
             } else {
-                fallback += 1;
+                fallback += tiled ? 1u : 0u;
                 float wd[DIM][3];  // w (o - f)
 #pragma unroll
                 for (int a = 0; a < DIM; ++a)
@@ -646,12 +689,14 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
             float qv[DIM], qC[D2], qF[N3];
             encode_record<DIM, RS, MAT>(sch, xn, nv, Cn, Fn, rnd, os, ls, qx, qv, qC, qF);
             // P2G of the stored (quantized) state for the next substep (Eq. 1)
-            if (do_p2g) p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback, clamped);
+            if (do_p2g)
+                p2g_particle<DIM, MAT>(P, qx, qv, qC, qF, origin, acc, gnxt, flags, fallback, clamped, tiled);
         }
         __syncthreads();
         // the velocity tile is free now: it holds the flush's node table
         static_assert(DIM * TN * sizeof(float) >= TN * (sizeof(uint32_t) + 1), "node table fits the velocity tile");
-        if (do_p2g) tile_flush<DIM>(P, origin, acc, gnxt, flags, touched, reinterpret_cast<uint32_t *>(gv));
+        if (do_p2g && tiled)
+            tile_flush<DIM>(P, origin, acc, gnxt, flags, touched, natom, reinterpret_cast<uint32_t *>(gv));
         if (collect_stats) {
             flush_stats(ls, stats);
             ls.clear();
@@ -659,6 +704,46 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
     }
     add_stat(stats, ST_FALLBACK, fallback);
     add_stat(stats, ST_CLAMP, clamped);
+    add_stat(stats, ST_ATOMICS, natom);
+}
+
+template <int DIM, bool RS, int MAT>
+__global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevScheme *__restrict__ sch, DevParams Parg, uint32_t *words,
+                                                int64_t cap_arg, const WorkItem *__restrict__ items,
+                                                const uint32_t *__restrict__ n_items,
+                                                const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
+                                                uint32_t *__restrict__ flags, uint32_t step, int do_p2g,
+                                                int collect_stats, uint64_t *stats) {
+    constexpr int TN = Geo<DIM>::TN;
+    __shared__ float gv[DIM * TN];
+    __shared__ unsigned long long acc[4 * TN];
+    __shared__ uint32_t touched[27];
+    if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
+    const ItemWalk walk(*n_items);
+    substep_items<DIM, RS, MAT>(sch, params_ref(Parg), words, cap_ref(cap_arg), items, walk, gcur, gnxt, flags,
+                                step, do_p2g, collect_stats, stats, gv, acc, touched);
+}
+
+// Batched substep of several scenes (serving): work-group g belongs to the
+// scene i with group_begin[i] <= g < group_begin[i + 1] and walks that
+// scene's work items as the per-scene launch would (same arithmetic, the
+// scene's own scheme, parameters, buffers, step and Philox key).
+template <int DIM, bool RS, int MAT>
+__global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep_batch(const BatchArgs args) {
+    constexpr int TN = Geo<DIM>::TN;
+    __shared__ float gv[DIM * TN];
+    __shared__ unsigned long long acc[4 * TN];
+    __shared__ uint32_t touched[27];
+    if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
+    const int i = batch_scene(args, blockIdx.x);
+    const BatchRef d = batch_ref(args.desc[i]);
+    const DevParams P = batch_params(d);
+    const uint32_t g0 = args.group_begin[i];
+    const ItemWalk walk(*d->n_items, blockIdx.x - g0, args.group_begin[i + 1] - g0);
+    const uint32_t step = args.step[i];
+    substep_items<DIM, RS, MAT>(d->scheme, P, d->words, d->cap, d->items, walk, d->grid[step & 1],
+                                d->grid[(step & 1) ^ 1], d->flags[(step & 1) ^ 1], step, args.mode[i] & 1,
+                                (args.mode[i] >> 1) & 1, d->stats, gv, acc, touched);
 }
 
 

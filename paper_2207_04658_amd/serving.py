@@ -10,6 +10,18 @@ memory.  Every scene keeps its own packed state resident on the device, its
 own Philox key (scheme seed) and slot numbering, so its result does not
 depend on which other scenes share the GPU.
 
+Two ways to issue the substeps of a tick:
+  - batched (default): scenes are spread over a few streams at admission,
+    and the scenes of one stream, dimension and material advance together
+    through mpmq_step_batch, one grid-update launch and one fused-substep
+    launch per substep for the whole set (continuous batching: a scene
+    admitted between ticks joins the next tick's batch of its stream, a
+    finished one leaves it; the streams let one batch's tail overlap
+    another's work and admissions run beside the batches);
+  - per scene (batched=False): one context per scene on a pool of streams,
+    each with its own launches.
+Either way a scene computes the same words bit for bit.
+
 Latency of a scene = time from its submission (its arrival) to the GPU
 completing its last substep, measured with HIP events on its stream against
 an event recorded when the server starts.
@@ -22,7 +34,7 @@ import collections
 import time
 from dataclasses import dataclass, field
 
-from . import Context, mpmq_query_sizes
+from . import Context, mpmq_query_sizes, step_batch
 
 
 def scene_bytes(scene: dict) -> int:
@@ -68,10 +80,12 @@ class ServeResult:
 class Server:
     """Admits scenes under an HBM budget and steps them in ticks."""
 
-    def __init__(self, hbm_budget_bytes=200e9, streams=8, steps_per_tick=10, keep_words=False, device=None):
+    def __init__(self, hbm_budget_bytes=200e9, streams=4, steps_per_tick=10, keep_words=False, device=None,
+                 batched=True):
         import torch
         self.budget = float(hbm_budget_bytes)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.batched = bool(batched)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(int(streams))]
         self.steps_per_tick = int(steps_per_tick)
         self.keep_words = keep_words
@@ -137,19 +151,38 @@ class Server:
             # one tick: every active scene with fewer than two ticks in flight
             # gets `steps_per_tick` more substeps
             progressed = False
+            due = []
             for a in active:
                 while a.inflight and a.inflight[0].query():
                     a.inflight.popleft()
                 if a.done_steps >= a.scene["steps"] or len(a.inflight) >= 2:
                     continue
-                k = min(self.steps_per_tick, a.scene["steps"] - a.done_steps)
-                a.ctx.step(k)
-                a.done_steps += k
-                ev = torch.cuda.Event(enable_timing=True)
-                ev.record(a.stream)
-                a.last_event = ev
-                a.inflight.append(ev)
-                progressed = True
+                due.append(a)
+            if self.batched:
+                # scenes of one dimension, material and substep count go out together
+                groups = collections.defaultdict(list)
+                for a in due:
+                    k = min(self.steps_per_tick, a.scene["steps"] - a.done_steps)
+                    groups[(id(a.stream), a.ctx.dim, a.ctx.f3, k)].append(a)
+                for (_, _, _, k), grp in groups.items():
+                    step_batch([a.ctx for a in grp], k)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(grp[0].stream)
+                    for a in grp:
+                        a.done_steps += k
+                        a.last_event = ev
+                        a.inflight.append(ev)
+                    progressed = True
+            else:
+                for a in due:
+                    k = min(self.steps_per_tick, a.scene["steps"] - a.done_steps)
+                    a.ctx.step(k)
+                    a.done_steps += k
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(a.stream)
+                    a.last_event = ev
+                    a.inflight.append(ev)
+                    progressed = True
             # retire finished scenes
             still = []
             for a in active:
