@@ -22,11 +22,14 @@ namespace mpmq {
 // each side beyond the 3-node stencil reach, so particles that drifted by up
 // to one cell since the sort stay inside the tile).
 template <int DIM> struct Geo;
+// TS: stride of the four component arrays of the LDS accumulator tile, TN + 8
+// nodes, so that the flush's lanes (16 nodes x 4 components per wave) spread
+// over all 64 LDS banks.
 template <> struct Geo<3> {
-    static constexpr int BLK = 8, LOG = 3, CPB = 512, TB = 12, TN = 1728, NST = 27;
+    static constexpr int BLK = 8, LOG = 3, CPB = 512, TB = 12, TN = 1728, TS = 1736, NST = 27;
 };
 template <> struct Geo<2> {
-    static constexpr int BLK = 16, LOG = 4, CPB = 256, TB = 20, TN = 400, NST = 9;
+    static constexpr int BLK = 16, LOG = 4, CPB = 256, TB = 20, TN = 400, TS = 408, NST = 9;
 };
 
 constexpr int WG = 256;          // threads per work-group of the particle kernels

@@ -104,7 +104,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                                              unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
                                              uint32_t *__restrict__ flags, uint32_t &fallback,
                                              uint32_t &clamped, const bool tile_ok = true) {
-    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
+    constexpr int TB = Geo<DIM>::TB, TS = Geo<DIM>::TS, D2 = DIM * DIM;
     // |q|, |a_b| <= 2^12 keeps a node value q + sum_b a_b o_b below 2^15
     // (2^47 in fixed point), so a node sum of up to 2^16 contributions stays
     // inside int64.  A particle with a larger term is clamped and counted
@@ -205,8 +205,8 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                         const double wt = wzy * w[0][ox];
                         const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TN + idx], fixr(wt, val[a]));
-                        atomicAdd(&acc[3 * TN + idx], fixr(w[0][ox], m32));
+                        for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TS + idx], fixr(wt, val[a]));
+                        atomicAdd(&acc[3 * TS + idx], fixr(w[0][ox], m32));
                     }
                 }
             }
@@ -227,8 +227,8 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
                     const double wt = w[1][oy] * w[0][ox];
                     const int idx = l0 + oy * TB + ox;
 #pragma unroll
-                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TN + idx], fixr(wt, val[a]));
-                    atomicAdd(&acc[3 * TN + idx], fixr(w[0][ox], m32));
+                    for (int a = 0; a < 2; ++a) atomicAdd(&acc[a * TS + idx], fixr(wt, val[a]));
+                    atomicAdd(&acc[3 * TS + idx], fixr(w[0][ox], m32));
                 }
             }
         }
@@ -303,7 +303,7 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
                                            const unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
                                            uint32_t *__restrict__ flags, uint32_t *touched, uint32_t &natom,
                                            uint32_t *__restrict__ table = nullptr) {
-    constexpr int TN = Geo<DIM>::TN, TB = Geo<DIM>::TB, B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
+    constexpr int TN = Geo<DIM>::TN, TS = Geo<DIM>::TS, TB = Geo<DIM>::TB, B = Geo<DIM>::BLK, L = Geo<DIM>::LOG;
     unsigned char *code = reinterpret_cast<unsigned char *>(table + TN);
     if (table) {
         // node index < 1024^3 fits 32 bits; 0xffffffff: outside the grid
@@ -320,9 +320,9 @@ __device__ __forceinline__ void tile_flush(const DevParams &P, const int *origin
     // covers whole cache lines (16 nodes) instead of 64 scattered words
     for (int q = threadIdx.x; q < 4 * TN; q += PWG) {
         const int t = q >> 2, c = q & 3;
-        const unsigned long long raw = acc[c * TN + t];
+        const unsigned long long raw = acc[c * TS + t];
         if (raw == 0ull) continue;  // no terms (a node with terms has a non-zero offset)
-        const unsigned long long sum = raw - (acc[3 * TN + t] & RAW_OFFSET_MASK);
+        const unsigned long long sum = raw - (acc[3 * TS + t] & RAW_OFFSET_MASK);
         if (sum != 0ull) {
             if (table) {
                 const uint32_t id = table[t];
@@ -421,8 +421,8 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
                                             uint32_t *__restrict__ flags, uint64_t *stats) {
     const DevParams &P = params_ref(Parg);
     const int64_t cap = cap_ref(cap_arg);
-    constexpr int TN = Geo<DIM>::TN, D2 = DIM * DIM;
-    __shared__ unsigned long long acc[4 * TN];
+    constexpr int TS = Geo<DIM>::TS, D2 = DIM * DIM;
+    __shared__ unsigned long long acc[4 * TS];
     __shared__ uint32_t touched[27];
     if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const uint32_t nit = *n_items;
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
         tile_origin<DIM>(it.block, P.nb, origin);
         __syncthreads();
         if (tiled)
-            for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
+            for (int t = threadIdx.x; t < 4 * TS; t += PWG) acc[t] = 0ull;
         __syncthreads();
         for (int p = it.p0 + threadIdx.x; p < it.p1; p += PWG) {
             double xd[DIM];
@@ -573,7 +573,7 @@ __device__ __forceinline__ void substep_items(const DevScheme *__restrict__ sch,
                                               GNode *__restrict__ gnxt, uint32_t *__restrict__ flags, uint32_t step,
                                               int do_p2g, int collect_stats, uint64_t *stats, float *gv,
                                               unsigned long long *acc, uint32_t *touched) {
-    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, D2 = DIM * DIM;
+    constexpr int TB = Geo<DIM>::TB, TN = Geo<DIM>::TN, TS = Geo<DIM>::TS, D2 = DIM * DIM;
     uint32_t fallback = 0, clamped = 0, natom = 0;
     LaneStats ls;
     ls.clear();
@@ -594,7 +594,7 @@ __device__ __forceinline__ void substep_items(const DevScheme *__restrict__ sch,
                 if constexpr (DIM == 3) gv[2 * TN + t] = g.z;
             }
             if (do_p2g)
-                for (int t = threadIdx.x; t < 4 * TN; t += PWG) acc[t] = 0ull;
+                for (int t = threadIdx.x; t < 4 * TS; t += PWG) acc[t] = 0ull;
         }
         __syncthreads();
 #ifdef MPMQ_SCHEME_CONST
@@ -714,9 +714,9 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
                                                 const GNode *__restrict__ gcur, GNode *__restrict__ gnxt,
                                                 uint32_t *__restrict__ flags, uint32_t step, int do_p2g,
                                                 int collect_stats, uint64_t *stats) {
-    constexpr int TN = Geo<DIM>::TN;
+    constexpr int TN = Geo<DIM>::TN, TS = Geo<DIM>::TS;
     __shared__ float gv[DIM * TN];
-    __shared__ unsigned long long acc[4 * TN];
+    __shared__ unsigned long long acc[4 * TS];
     __shared__ uint32_t touched[27];
     if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const ItemWalk walk(*n_items);
@@ -730,9 +730,9 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep(const DevSche
 // scene's own scheme, parameters, buffers, step and Philox key).
 template <int DIM, bool RS, int MAT>
 __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_substep_batch(const BatchArgs args) {
-    constexpr int TN = Geo<DIM>::TN;
+    constexpr int TN = Geo<DIM>::TN, TS = Geo<DIM>::TS;
     __shared__ float gv[DIM * TN];
-    __shared__ unsigned long long acc[4 * TN];
+    __shared__ unsigned long long acc[4 * TS];
     __shared__ uint32_t touched[27];
     if (threadIdx.x < 27) touched[threadIdx.x] = 0u;
     const int i = batch_scene(args, blockIdx.x);
