@@ -58,7 +58,7 @@ __device__ __forceinline__ void stress_vjp(const DevParams &P, const float *F, c
     constexpr int D2 = DIM * DIM;
     float R[D2], S[D2], Cf[D2];
     if constexpr (DIM == 2) polar2(F, R);
-    else polar3(F, R);
+    else polar3<true>(F, R);
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
@@ -580,7 +580,7 @@ __device__ __forceinline__ void adj_p2g_particle(const DevScheme *__restrict__ s
     } else {
         float R[D2];
         if constexpr (DIM == 2) polar2(F, R);
-        else polar3(F, R);
+        else polar3<true>(F, R);
         const float J = det_f<DIM>(F);
 #pragma unroll
         for (int i = 0; i < DIM; ++i)

@@ -563,29 +563,27 @@ __device__ __forceinline__ void polar2(const float *F, float *R) {
     R[0] = c; R[1] = -s; R[2] = s; R[3] = c;
 }
 
-// One Jacobi rotation in the (P, Q) plane of the symmetric 3x3 matrix A
-// (row-major, indices compile-time constants so the arrays stay in
-// registers): A <- J^T A J zeroes A[P][Q]; V <- V J accumulates the
-// eigenvectors as columns.
+// One Jacobi rotation of the symmetric 3x3 matrix held as its six distinct
+// entries a = (a00, a01, a02, a11, a12, a22), in the (P, Q) plane (R the
+// third index; all compile-time constants, so everything stays in
+// registers): the angle zeroes a_PQ (tan from theta = (a_QQ - a_PP) / 2 a_PQ,
+// the smaller root); V <- V J accumulates the eigenvectors as columns.
 template <int P, int Q>
-__device__ __forceinline__ void jacobi_rot3(float *A, float *V) {
-    const float apq = A[P * 3 + Q];
+__device__ __forceinline__ void jacobi_rot3(float *a, float *V) {
+    constexpr int R = 3 - P - Q;
+    constexpr int ix[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    const float apq = a[ix[P][Q]];
     if (apq == 0.0f) return;
-    const float theta = (A[Q * 3 + Q] - A[P * 3 + P]) / (2.0f * apq);
+    const float app = a[ix[P][P]], aqq = a[ix[Q][Q]];
+    const float theta = (aqq - app) / (2.0f * apq);
     const float t = (theta >= 0.0f ? 1.0f : -1.0f) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
     const float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float akp = A[k * 3 + P], akq = A[k * 3 + Q];
-        A[k * 3 + P] = c * akp - s * akq;
-        A[k * 3 + Q] = s * akp + c * akq;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float apk = A[P * 3 + k], aqk = A[Q * 3 + k];
-        A[P * 3 + k] = c * apk - s * aqk;
-        A[Q * 3 + k] = s * apk + c * aqk;
-    }
+    const float arp = a[ix[R][P]], arq = a[ix[R][Q]];
+    a[ix[P][P]] = app - t * apq;
+    a[ix[Q][Q]] = aqq + t * apq;
+    a[ix[P][Q]] = 0.0f;
+    a[ix[R][P]] = c * arp - s * arq;
+    a[ix[R][Q]] = s * arp + c * arq;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float vkp = V[k * 3 + P], vkq = V[k * 3 + Q];
@@ -608,99 +606,107 @@ __device__ __forceinline__ void normalize3f(float *a) {
     }
 }
 
+// Swaps eigenpairs a < b (compile-time) when lam[b] > lam[a]; V's columns.
+template <int A, int B>
+__device__ __forceinline__ void order_pair(float *lam, float *V) {
+    if (lam[B] > lam[A]) {
+        const float t = lam[A]; lam[A] = lam[B]; lam[B] = t;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float u = V[k * 3 + A]; V[k * 3 + A] = V[k * 3 + B]; V[k * 3 + B] = u;
+        }
+    }
+}
+
 // Closest rotation to F from its singular value decomposition, for F that
 // is inverted or nearly singular (there Newton's iteration below either
 // converges to a reflection or not at all).  F^T F = V diag(sigma^2) V^T by
 // cyclic Jacobi sweeps; the singular directions are ordered by decreasing
-// sigma and V made a proper rotation; u_a = F v_a / sigma_a for the two
-// largest (Gram-Schmidt), u_3 = u_1 x u_2; R = U V^T.  R is then the
-// fixed-corotated model's rotation: det R = +1, with the reflection of an
+// sigma and V made a proper rotation (v_3 = v_1 x v_2); u_a = F v_a / sigma_a
+// for the two largest (Gram-Schmidt), u_3 = u_1 x u_2; R = U V^T.  R is then
+// the fixed-corotated model's rotation: det R = +1, with the reflection of an
 // inverted F carried by the direction of its smallest singular value.
 __device__ __forceinline__ void polar3_svd(const float *F, float *R) {
-    float A[9], V[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    float a[6], V[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    {
+        int k = 0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) A[i * 3 + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
-    for (int sweep = 0; sweep < 12; ++sweep) {
-        const float off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
-        const float diag = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
-        if (!(off > 1e-14f * diag)) break;
-        jacobi_rot3<0, 1>(A, V);
-        jacobi_rot3<0, 2>(A, V);
-        jacobi_rot3<1, 2>(A, V);
+            for (int j = i; j < 3; ++j) a[k++] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
     }
-    // eigenvalues with their eigenvector columns, sorted by decreasing value
-    float lam[3] = {A[0], A[4], A[8]};
-    float v[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v[a][k] = V[k * 3 + a];
-    auto order = [&](int a, int b) {
-        // a < b are compile-time constants after unrolling
-        if (lam[b] > lam[a]) {
-            const float t = lam[a]; lam[a] = lam[b]; lam[b] = t;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) { const float u = v[a][k]; v[a][k] = v[b][k]; v[b][k] = u; }
-        }
-    };
-    order(0, 1);
-    order(0, 2);
-    order(1, 2);
-    float vc[3];
-    cross3f(v[0], v[1], vc);
-    if (vc[0] * v[2][0] + vc[1] * v[2][1] + vc[2] * v[2][2] < 0.0f)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v[2][k] = -v[2][k];
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        const float off = a[1] * a[1] + a[2] * a[2] + a[4] * a[4];
+        const float diag = a[0] * a[0] + a[3] * a[3] + a[5] * a[5];
+        if (!(off > 1e-14f * diag)) break;
+        jacobi_rot3<0, 1>(a, V);
+        jacobi_rot3<0, 2>(a, V);
+        jacobi_rot3<1, 2>(a, V);
+    }
+    // eigenvalues with their eigenvector columns, by decreasing value
+    float lam[3] = {a[0], a[3], a[5]};
+    order_pair<0, 1>(lam, V);
+    order_pair<0, 2>(lam, V);
+    order_pair<1, 2>(lam, V);
+    {
+        const float v0[3] = {V[0], V[3], V[6]}, v1[3] = {V[1], V[4], V[7]};
+        float v2[3];
+        cross3f(v0, v1, v2);
+        V[2] = v2[0]; V[5] = v2[1]; V[8] = v2[2];
+    }
     const float s0 = sqrtf(fmaxf(lam[0], 0.0f)), s1 = sqrtf(fmaxf(lam[1], 0.0f));
     if (!(s0 > 0.0f)) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0f : 0.0f;
         return;
     }
-    float u[3][3];
+    float u0[3], u1[3];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int k = 0; k < 3; ++k) {
+        u0[k] = F[k * 3] * V[0] + F[k * 3 + 1] * V[3] + F[k * 3 + 2] * V[6];
+        u1[k] = F[k * 3] * V[1] + F[k * 3 + 1] * V[4] + F[k * 3 + 2] * V[7];
+    }
+    normalize3f(u0);
+    const float d = u1[0] * u0[0] + u1[1] * u0[1] + u1[2] * u0[2];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) u[a][k] = F[k * 3] * v[a][0] + F[k * 3 + 1] * v[a][1] + F[k * 3 + 2] * v[a][2];
-    normalize3f(u[0]);
-    const float d = u[1][0] * u[0][0] + u[1][1] * u[0][1] + u[1][2] * u[0][2];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) u[1][k] -= d * u[0][k];
-    const float n1 = sqrtf(u[1][0] * u[1][0] + u[1][1] * u[1][1] + u[1][2] * u[1][2]);
+    for (int k = 0; k < 3; ++k) u1[k] -= d * u0[k];
+    const float n1 = sqrtf(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
     if (!(s1 > 1e-30f) || !(n1 > 1e-5f * s0)) {
         // rank one: any unit vector orthogonal to u_1 (from the axis least aligned with it)
-        const float ax = fabsf(u[0][0]), ay = fabsf(u[0][1]), az = fabsf(u[0][2]);
+        const float ax = fabsf(u0[0]), ay = fabsf(u0[1]), az = fabsf(u0[2]);
         float e[3] = {0.0f, 0.0f, 0.0f};
         if (ax <= ay && ax <= az) e[0] = 1.0f;
         else if (ay <= az) e[1] = 1.0f;
         else e[2] = 1.0f;
-        cross3f(u[0], e, u[1]);
+        cross3f(u0, e, u1);
     }
-    normalize3f(u[1]);
-    cross3f(u[0], u[1], u[2]);
+    normalize3f(u1);
+    float u2[3];
+    cross3f(u0, u1, u2);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) R[i * 3 + j] = u[0][i] * v[0][j] + u[1][i] * v[1][j] + u[2][i] * v[2][j];
+        for (int j = 0; j < 3; ++j) R[i * 3 + j] = u0[i] * V[j * 3] + u1[i] * V[j * 3 + 1] + u2[i] * V[j * 3 + 2];
 }
 
+// The SVD branch as a called function: a kernel near an occupancy step of
+// its register count keeps the branch's registers out of its own allocation
+// (the call is taken by the rare lanes only).
+static __device__ __attribute__((noinline)) void polar3_svd_call(const float *F, float *R) { polar3_svd(F, R); }
+
+// Newton's iteration R <- (R + R^-T) / 2 from R = F converges to the
+// orthogonal polar factor, which is the closest rotation when det F > 0.
+// Lanes where it does not deliver that rotation -- an inverted F (the limit
+// is a reflection, det R = -1), a singular or degenerate F (a vanishing
+// determinant on the way) or no convergence within 16 steps -- take the SVD
+// above, after the iteration (which then holds no extra state).  OUTLINE:
+// call the SVD instead of inlining it.
+template <bool OUTLINE = false>
 __device__ __forceinline__ void polar3(const float *F, float *R) {
-    // Newton's iteration keeps the sign of det F: it is used where F is
-    // well inside the proper rotations' side (det F above 1e-3 of the
-    // determinant of a rotation of the same size); the other lanes -- an
-    // inverted, flattened or zero F -- take the SVD above (a rare branch)
-    const float n2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2] + F[3] * F[3] + F[4] * F[4] + F[5] * F[5] +
-                     F[6] * F[6] + F[7] * F[7] + F[8] * F[8];
-    const float detF = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
-                       F[2] * (F[3] * F[7] - F[4] * F[6]);
-    const float s3 = n2 * (1.0f / 3.0f);
-    // (a Newton lane then has det F >= 1e-20, so every reciprocal below is
-    // finite; its iterates keep a determinant of at least min(det F, 1))
-    const bool svd = detF <= 1e-3f * s3 * sqrtf(s3) || detF < 1e-20f;  // NaN F: false (Newton, NaN out)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) R[i] = svd ? ((i % 4 == 0) ? 1.0f : 0.0f) : F[i];
+    for (int i = 0; i < 9; ++i) R[i] = F[i];
+    bool bad = false;
+    float d2 = 0.0f;
     for (int it = 0; it < 16; ++it) {
         // cofactor matrix = det * R^-T
         const float c00 = R[4] * R[8] - R[5] * R[7], c01 = R[5] * R[6] - R[3] * R[8],
@@ -710,24 +716,32 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
         const float c20 = R[1] * R[5] - R[2] * R[4], c21 = R[2] * R[3] - R[0] * R[5],
                     c22 = R[0] * R[4] - R[1] * R[3];
         const float det = R[0] * c00 + R[1] * c01 + R[2] * c02;
+        const bool ok = fabsf(det) > 1e-20f;
+        bad |= !ok;
         // hardware reciprocal (1 ulp): the iteration absorbs its error
-        const float hid = 0.5f * __builtin_amdgcn_rcpf(det);
+        const float hid = ok ? 0.5f * __builtin_amdgcn_rcpf(det) : 0.0f;
         float Rn[9] = {0.5f * R[0] + hid * c00, 0.5f * R[1] + hid * c01, 0.5f * R[2] + hid * c02,
                        0.5f * R[3] + hid * c10, 0.5f * R[4] + hid * c11, 0.5f * R[5] + hid * c12,
                        0.5f * R[6] + hid * c20, 0.5f * R[7] + hid * c21, 0.5f * R[8] + hid * c22};
-        float d2 = 0.0f;
+        d2 = 0.0f;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const float d = Rn[i] - R[i];
             d2 += d * d;
-            R[i] = Rn[i];
+            R[i] = ok ? Rn[i] : ((i % 4 == 0) ? 1.0f : 0.0f);
         }
         // Newton's polar iteration converges quadratically: the error of the
         // new iterate is about |R_new - R|^2 / (2 sigma_min), below 1e-8 once
         // the step is under 1e-4, below float precision
         if (!__any(d2 > 1e-8f)) break;
     }
-    if (svd) polar3_svd(F, R);
+    const float detR = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                       R[2] * (R[3] * R[7] - R[4] * R[6]);
+    bad |= !(detR > 0.5f) || d2 > 1e-8f;
+    if (bad) {
+        if constexpr (OUTLINE) polar3_svd_call(F, R);
+        else polar3_svd(F, R);
+    }
 }
 
 }  // namespace mpmq

@@ -98,7 +98,8 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
 // order-independent).  The tile takes raw terms (fixr); the offset comes
 // off at the flush.
 // ---------------------------------------------------------------------------
-template <int DIM, int MAT>
+// OUTLINE: the polar decomposition's rare SVD branch as a call (see polar3).
+template <int DIM, int MAT, bool OUTLINE = false>
 __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
                                              const float *C, const float *F, const int *origin,
                                              unsigned long long *__restrict__ acc, GNode *__restrict__ gout,
@@ -138,7 +139,7 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
             polar2(F, R);
             J = F[0] * F[3] - F[1] * F[2];
         } else {
-            polar3(F, R);
+            polar3<OUTLINE>(F, R);
             J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
                 F[2] * (F[3] * F[7] - F[4] * F[6]);
         }
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
             double xd[DIM];
             float v[DIM], C[D2], F[nc3<DIM, MAT>()];
             decode_all<DIM, float, MAT>(sch, words, cap, (uint32_t)p * 4u, xd, v, C, F);
-            p2g_particle<DIM, MAT>(P, xd, v, C, F, origin, acc, gout, flags, fallback, clamped, tiled);
+            p2g_particle<DIM, MAT, true>(P, xd, v, C, F, origin, acc, gout, flags, fallback, clamped, tiled);
         }
         __syncthreads();
         if (tiled) tile_flush<DIM>(P, origin, acc, gout, flags, touched, natom);
