@@ -260,11 +260,10 @@ def cpu_baseline(scene):
     model, usable, logical = host_cpu()
     if scene["name"] == "c3":
         sub = WL.c3(only=[0])
-        sample = (f"cube 0 of 186 ({sub['n']} particles) on the full 512^3 grid, 3 substeps after a "
-                  f"warm-up substep that includes the sort")
+        sample = f"cube 0 of 186 ({sub['n']} particles) on the full 512^3 grid"
     elif scene["name"] == "c2":
         sub = WL.c2(cubes=1)
-        sample = f"cube 0 of 4 ({sub['n']} particles) on the 128^3 grid, 3 substeps after a warm-up substep"
+        sample = f"cube 0 of 4 ({sub['n']} particles) on the 128^3 grid"
     elif scene["name"] == "fluid":
         # a slab x in [0.1, 0.1075) of the column at the same density (8 per cell) on the 512^3 grid
         rng = np.random.default_rng(3)
@@ -273,11 +272,10 @@ def cpu_baseline(scene):
         xs = (lo[:, None] + (hi - lo)[:, None] * rng.random((3, ns))).astype(np.float32)
         state = (xs, np.zeros((3, ns), np.float32), np.zeros((9, ns), np.float32), np.ones((1, ns), np.float32))
         sub = {"scheme": scene["scheme"], "params": scene["params"], "n": ns, "state": state}
-        sample = (f"a slab of {ns} particles of the dam-break column (same density) on the full 512^3 grid, "
-                  f"3 substeps after a warm-up substep")
+        sample = f"a slab of {ns} particles of the dam-break column (same density) on the full 512^3 grid"
     else:
         sub = WL.c1()
-        sample = "the full scene (8192 particles), 3 substeps after a warm-up substep"
+        sample = "the full scene (8192 particles)"
     x, v, C, F = sub["state"]
     words, _ = oracle.encode(sub["scheme"], x, v, C, F, 0, 2)
     sim = oracle.Sim(sub["scheme"], sub["params"], words)
@@ -291,7 +289,8 @@ def cpu_baseline(scene):
     med = float(np.median(times))
     single = sub["n"] / med
     out = {"value": single, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-           "sample": sample + " (median of three timed substeps)", "seconds": round(sum(times), 3),
+           "sample": sample + ": one warm-up substep (with the sort), then the median of three timed substeps",
+           "seconds": round(sum(times), 3),
            "host_cpu": model, "usable_cores": usable, "logical_cpus": logical,
            "single_thread": {"value": round(single, 1), "substep_s": [round(t, 3) for t in times]}}
     if scene["name"] == "c3" and usable > 1:
