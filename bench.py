@@ -568,6 +568,7 @@ def main():
     line["saturations"] = {k: main_res["stats"][k]["sat"] for k in fields}
     line["nan"] = {k: main_res["stats"][k]["nan"] for k in fields}
     line["fallback_stencils"] = main_res["stats"]["fallback"]
+    line["wide_scatters"] = main_res["stats"]["wide"]
     print(json.dumps(line), flush=True)
 
 

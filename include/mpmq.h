@@ -148,6 +148,9 @@ typedef struct {
                           fixed-point node sums cannot overflow (the clamp loses momentum) */
     int64_t atomics;   /* 64-bit global atomic adds issued by the P2G tile flushes (the
                           scatter of each work item's node sums into the grid) */
+    int64_t wide;      /* particle scatters of the fused substep whose node values lay too
+                          far from their work item's reference velocity for its 32-bit node
+                          tile, scattered through the 64-bit global path instead */
 } mpmq_stats_t;
 
 typedef struct mpmq_ctx mpmq_ctx;
@@ -212,7 +215,17 @@ mpmq_status mpmq_step_count(mpmq_ctx *ctx, int64_t *out);
  * compile-time constants (field kinds, bit offsets, masks, codec constants;
  * the Philox key stays a run-time value), loads them on the current device
  * and uses them from the next launch on.  The kernels are the same source
- * under the same device flags, so every result equals the generic kernels'.
+ * under the same device flags, with one difference: the specialized fused
+ * kernel accumulates P2G in a 32-bit node tile per work item (node values
+ * less a reference velocity, at a scale chosen per item, 48 KB of LDS in 3D
+ * so that three work-groups share a CU), the generic one in an exact 64-bit
+ * tile.  Where no fused P2G is involved (a sort before every substep)
+ * results are bit-identical; otherwise they differ by the 32-bit tile's
+ * roundings, of the order of float32 noise in the node velocities.  A
+ * particle whose node values do not fit its item's 32-bit range is scattered
+ * through the exact global path (mpmq_stats_t.wide).  Either way a run is
+ * bit-reproducible, and the adjoint's recomputation reproduces the forward
+ * pass: the scales each item used are recorded with the stored state.
  * Code objects are cached per process by (device, dimension, scheme): the
  * first call for a scheme takes a few seconds, later ones none.  enable = 0
  * returns to the generic kernels.  EDEVICE when the compiler or the loader

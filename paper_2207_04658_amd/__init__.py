@@ -74,7 +74,7 @@ class mpmq_stats_t(ct.Structure):
     _fields_ = [("sat", ct.c_int64 * 4), ("nan", ct.c_int64 * 4), ("up", ct.c_int64 * 4),
                 ("down", ct.c_int64 * 4), ("steps", ct.c_int64), ("sorts", ct.c_int64),
                 ("fallback", ct.c_int64), ("active_nodes", ct.c_int64), ("clamped", ct.c_int64),
-                ("atomics", ct.c_int64)]
+                ("atomics", ct.c_int64), ("wide", ct.c_int64)]
 
 
 class mpmq_kernel_time(ct.Structure):
@@ -330,7 +330,7 @@ class Context:
         out = {names[i]: {"sat": st.sat[i], "nan": st.nan[i], "up": st.up[i], "down": st.down[i]}
                for i in range(4)}
         out.update(steps=st.steps, sorts=st.sorts, fallback=st.fallback, active_nodes=st.active_nodes,
-                   clamped=st.clamped, atomics=st.atomics)
+                   clamped=st.clamped, atomics=st.atomics, wide=st.wide)
         return out
 
     def set_stats(self, level):

@@ -623,14 +623,15 @@ hipError_t launch_items(const uint32_t *cell_start, const uint32_t *item_off, in
 
 hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, const uint32_t *words, int64_t cap,
                       const WorkItem *items, const uint32_t *n_items, int grid, GNode *gout, uint32_t *flags_out,
-                      uint64_t *stats, hipStream_t st, const JitKernels *jit) {
+                      const TileScale *iscale, float4 *irec, uint64_t *stats, hipStream_t st, const JitKernels *jit) {
     if (jit && jit->p2g) {
         DevParams pv = p;
         void *args[] = {(void *)&s, &pv, (void *)&words, &cap, (void *)&items, (void *)&n_items, &gout, &flags_out,
-                        &stats};
+                        (void *)&iscale, &irec, &stats};
         return hipModuleLaunchKernel(jit->p2g, (unsigned)grid, 1, 1, PWG, 1, 1, 0, st, args, nullptr);
     }
-    MPMQ_DISPATCH_MB(dim, mat, k_p2g, dim3(grid), PWG, s, p, words, cap, items, n_items, gout, flags_out, stats);
+    MPMQ_DISPATCH_MB(dim, mat, k_p2g, dim3(grid), PWG, s, p, words, cap, items, n_items, gout, flags_out, iscale,
+                     irec, stats);
     return hipGetLastError();
 }
 
@@ -678,21 +679,22 @@ hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblo
 
 hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams &p, uint32_t *words, int64_t cap,
                           const WorkItem *items, const uint32_t *n_items, int grid, const GNode *gcur,
-                          GNode *gnxt, uint32_t *flags_nxt, uint32_t step, int do_p2g, int collect_stats,
-                          int round_stats, uint64_t *stats, hipStream_t st, const JitKernels *jit) {
+                          GNode *gnxt, uint32_t *flags_nxt, TileScale *iscale, float4 *irec, uint32_t step,
+                          int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st,
+                          const JitKernels *jit) {
     if (jit && jit->substep[round_stats ? 1 : 0]) {
         DevParams pv = p;
         void *args[] = {(void *)&s, &pv, &words, &cap, (void *)&items, (void *)&n_items, (void *)&gcur, &gnxt,
-                        &flags_nxt, &step, &do_p2g, &collect_stats, &stats};
+                        &flags_nxt, &iscale, &irec, &step, &do_p2g, &collect_stats, &stats};
         return hipModuleLaunchKernel(jit->substep[round_stats ? 1 : 0], (unsigned)grid, 1, 1, PWG, 1, 1, 0, st, args,
                                      nullptr);
     }
     if (round_stats)
         MPMQ_DISPATCH2(dim, mat, k_substep, true, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
-                       step, do_p2g, collect_stats, stats);
+                       iscale, irec, step, do_p2g, collect_stats, stats);
     else
         MPMQ_DISPATCH2(dim, mat, k_substep, false, dim3(grid), s, p, words, cap, items, n_items, gcur, gnxt, flags_nxt,
-                       step, do_p2g, collect_stats, stats);
+                       iscale, irec, step, do_p2g, collect_stats, stats);
     return hipGetLastError();
 }
 

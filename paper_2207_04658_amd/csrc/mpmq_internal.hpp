@@ -82,10 +82,12 @@ struct DevParams {
 
 // Statistics slots (uint64) in scratch.  ST_CLAMP: particles whose P2G
 // terms were clamped to the fixed-point range (see p2g_particle);
-// ST_ATOMICS: 64-bit global atomic adds issued by the P2G tile flushes.
+// ST_ATOMICS: 64-bit global atomic adds issued by the P2G tile flushes;
+// ST_WIDE: particles of the fused kernel whose P2G terms did not fit their
+// work item's 32-bit node tile (scattered through the 64-bit global path).
 enum {
     ST_SAT = 0, ST_NAN = 4, ST_UP = 8, ST_DOWN = 12, ST_FALLBACK = 16, ST_ACTIVE = 17, ST_ACTIVE_SLOTS = 7,
-    ST_CLAMP = 24, ST_ATOMICS = 25, ST_COUNT = 26
+    ST_CLAMP = 24, ST_ATOMICS = 25, ST_WIDE = 26, ST_COUNT = 27
 };
 
 // Device scratch layout (byte offsets, all 256-aligned).
@@ -96,6 +98,8 @@ struct Scratch {
     int64_t hist;                        // radix histogram, 256 * tiles
     int64_t block_items;                 // nblocks + 1 item counts -> offsets
     int64_t items;                       // int4 work items
+    int64_t iscale;                      // TileScale per work item (P2G tile scales of the stored state)
+    int64_t irec;                        // float4 per work item: record of its last P2G (tile_scale)
     int64_t flags;                       // 2 * nblocks uint32 touched flags
     int64_t stats;                       // ST_COUNT uint64
     int64_t misc;                        // 64 uint32 (n_items, ...)
@@ -106,6 +110,19 @@ struct Scratch {
 };
 
 struct WorkItem { int32_t block, p0, p1, pad; };
+
+// Scales of a work item's 32-bit P2G node tile (see substep.hpp): node
+// values are summed less vref in units of 2^-s, weights in units of 2^-sm,
+// and a particle enters the tile only if its node values lie within lim_v
+// of vref.  The fused kernel records the scales each item used in a table
+// (one entry per work item) so that a later P2G of the same stored state
+// (the adjoint's recomputation from a checkpoint, a grid rebuilt after the
+// adjoint) reproduces its sums bit for bit.
+struct TileScale {
+    float vref[3];     // reference velocity, a multiple of 2^-(32 - sm), |vref| 2^(32 - sm) <= 2^24
+    float lim_v;       // admission bound of |node value - vref| (velocity units)
+    int32_t s, sm;     // exponents of the momentum and weight scales
+};
 
 // Batched launches (serving): a context's buffers and parameters, kept in its
 // scratch in device memory, and the per-launch table of scenes.
@@ -118,6 +135,8 @@ struct BatchDesc {
     GNode *grid[2];
     uint32_t *flags[2];
     uint64_t *stats;
+    TileScale *iscale;
+    float4 *irec;
     int64_t nblocks;
     DevParams P;
 };
@@ -165,10 +184,13 @@ struct JitKernels {
 // kernels for the current device.  Returns false with a message on failure.
 bool jit_kernels(int dim, const DevScheme &ds, const DevParams &dp, int64_t cap, JitKernels *out, std::string *err);
 
+// iscale: null for an exact 64-bit P2G (after a sort or an encode), else the
+// scales the fused kernel recorded when it scattered this state.
+// irec: receives each tiled work item's record (for the next fused substep).
 hipError_t launch_p2g(int dim, int mat, const DevScheme *s, const DevParams &p, const uint32_t *words,
                       int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
-                      GNode *gout, uint32_t *flags_out, uint64_t *stats, hipStream_t st,
-                      const JitKernels *jit = nullptr);
+                      GNode *gout, uint32_t *flags_out, const TileScale *iscale, float4 *irec,
+                      uint64_t *stats, hipStream_t st, const JitKernels *jit = nullptr);
 hipError_t launch_grid_update(int dim, const DevParams &p, GNode *gcur, GNode *gnxt,
                               uint32_t *flags_cur, uint32_t *flags_nxt, int64_t nblocks,
                               uint64_t *stats, hipStream_t st);
@@ -177,11 +199,13 @@ hipError_t launch_clear_touched(int dim, GNode *g, uint32_t *flags, int64_t nblo
 // material (group_begin counts the launch's work-groups per scene).
 hipError_t launch_grid_update_batch(int dim, const BatchArgs &a, hipStream_t st);
 hipError_t launch_substep_batch(int dim, int mat, int round_stats, const BatchArgs &a, hipStream_t st);
+// iscale: receives the tile scales of every work item that scatters (do_p2g);
+// irec: each item's record of its last P2G, read and rewritten.
 hipError_t launch_substep(int dim, int mat, const DevScheme *s, const DevParams &p, uint32_t *words,
                           int64_t cap, const WorkItem *items, const uint32_t *n_items, int grid,
-                          const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, uint32_t step,
-                          int do_p2g, int collect_stats, int round_stats, uint64_t *stats, hipStream_t st,
-                          const JitKernels *jit = nullptr);
+                          const GNode *gcur, GNode *gnxt, uint32_t *flags_nxt, TileScale *iscale,
+                          float4 *irec, uint32_t step, int do_p2g, int collect_stats, int round_stats,
+                          uint64_t *stats, hipStream_t st, const JitKernels *jit = nullptr);
 
 // Adjoint (adjoint.hip).  lam buffers: float32 rows x[d], v[d], C[d*d],
 // then F[d*d] (elastic) or J (fluid) of n each; nadj: one float4 per grid node; acc: binary64 z, G[4],

@@ -179,6 +179,8 @@ Scratch plan_scratch(int dim, int res, int64_t cap_pad) {
     s.hist = o; o = align256(o + 4 * s.hist_entries);
     s.block_items = o; o = align256(o + 4 * (s.nblocks + 1));
     s.items = o; o = align256(o + 16 * s.max_items);
+    s.iscale = o; o = align256(o + (int64_t)sizeof(TileScale) * s.max_items);
+    s.irec = o; o = align256(o + 16 * s.max_items);
     s.flags = o; o = align256(o + 4 * 2 * s.nblocks);
     s.stats = o; o = align256(o + 8 * ST_COUNT);
     s.misc = o; o = align256(o + 256);
@@ -204,6 +206,9 @@ struct mpmq_ctx {
     Scratch sp;
     int64_t n = 0, step = 0, sorted_at = -1, sorts = 0, steps_taken = 0;
     bool encoded = false, sorted = false, p2g_ready = false;
+    // the P2G tile scales of c->words are in iscale() (recorded by the fused
+    // kernel that stored it); false after a sort or an encode
+    bool scales_valid = false;
     int item_cap = 256, launch_grid = 1;
     bool timing = false;
     int stats_level = 0;
@@ -220,6 +225,8 @@ struct mpmq_ctx {
     uint32_t *flags(int i) { return u32(sp.flags) + (int64_t)i * sp.nblocks; }
     uint32_t *n_items() { return u32(sp.misc); }
     WorkItem *items() { return reinterpret_cast<WorkItem *>(scratch + sp.items); }
+    TileScale *iscale() { return reinterpret_cast<TileScale *>(scratch + sp.iscale); }
+    float4 *irec() { return reinterpret_cast<float4 *>(scratch + sp.irec); }
     const DevScheme *dscheme() { return reinterpret_cast<const DevScheme *>(scratch + sp.scheme); }
     const BatchDesc *dbatch() { return reinterpret_cast<const BatchDesc *>(scratch + sp.batch); }
 };
@@ -262,6 +269,7 @@ struct Timed {
 
 mpmq_status do_sort(mpmq_ctx *c) {
     hipStream_t st = c->stream;
+    c->scales_valid = false;  // new work items
     const int64_t n = c->n;
     const Scratch &s = c->sp;
     const int cpb = c->dim == 3 ? Geo<3>::CPB : Geo<2>::CPB;
@@ -339,7 +347,8 @@ mpmq_status pre_substep(mpmq_ctx *c, bool allow_sort) {
     if (!c->p2g_ready) {
         Timed t(c, "p2g");
         HIPCHK(c, launch_p2g(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
-                             c->launch_grid, c->grid[cur], c->flags(cur), c->stats(), st, c->jit_ptr()), "p2g");
+                             c->launch_grid, c->grid[cur], c->flags(cur), c->scales_valid ? c->iscale() : nullptr,
+                             c->irec(), c->stats(), st, c->jit_ptr()), "p2g");
     }
     return MPMQ_OK;
 }
@@ -352,8 +361,12 @@ bool next_sorts(const mpmq_ctx *c, bool allow_sort) {
 }
 
 // Host state after a substep's launches.
-void post_substep(mpmq_ctx *c, bool allow_sort) {
+// t32: the fused kernel that ran sums in the 32-bit node tile (the scheme-
+// specialized build) and recorded its tile scales; the generic build's
+// 64-bit sums are reproduced by an exact P2G.
+void post_substep(mpmq_ctx *c, bool allow_sort, bool t32) {
     c->p2g_ready = !next_sorts(c, allow_sort);
+    c->scales_valid = c->p2g_ready && t32;
     c->step += 1;
     c->steps_taken += 1;
 }
@@ -374,12 +387,14 @@ mpmq_status substep_once(mpmq_ctx *c, bool allow_sort) {
     {
         Timed t(c, "substep");
         HIPCHK(c, launch_substep(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, c->items(), c->n_items(),
-                                 c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), (uint32_t)s,
+                                 c->launch_grid, c->grid[cur], c->grid[nxt], c->flags(nxt), c->iscale(), c->irec(),
+                                 (uint32_t)s,
                                  next_sorts(c, allow_sort) ? 0 : 1, 1, c->stats_level >= 1 ? 1 : 0, c->stats(), st,
                                  c->jit_ptr()),
                "substep");
     }
-    post_substep(c, allow_sort);
+    const JitKernels *jk = c->jit_ptr();
+    post_substep(c, allow_sort, jk && jk->substep[c->stats_level >= 1 ? 1 : 0]);
     return MPMQ_OK;
 }
 
@@ -439,7 +454,7 @@ mpmq_status batch_substep(mpmq_ctx *const *all, int count_all) {
             }
         }
     }
-    for (int i = 0; i < count; ++i) post_substep(ctxs[i], true);
+    for (int i = 0; i < count; ++i) post_substep(ctxs[i], true, false);  // generic kernels
     return MPMQ_OK;
 }
 
@@ -494,8 +509,9 @@ AdjPlan adj_plan(int64_t T, int64_t K) {
 }
 
 struct AdjWork {
-    int64_t state_bytes = 0, lam_bytes = 0, nodes = 0;
-    int64_t off_states = 0, off_final = 0, off_lam = 0, off_nadj = 0, off_acc = 0, off_stats = 0, total = 0;
+    int64_t state_bytes = 0, scale_bytes = 0, lam_bytes = 0, nodes = 0;
+    int64_t off_states = 0, off_final = 0, off_scales = 0, off_lam = 0, off_nadj = 0, off_acc = 0, off_stats = 0,
+            total = 0;
 };
 
 AdjWork adj_layout(const mpmq_ctx *c, const AdjPlan &plan) {
@@ -505,8 +521,10 @@ AdjWork adj_layout(const mpmq_ctx *c, const AdjPlan &plan) {
     w.state_bytes = 4 * (int64_t)c->W * c->cap_pad;
     w.lam_bytes = align256(4 * (int64_t)adj_rows(c->dim, c->ds.mat) * std::max<int64_t>(c->n, 1));
     int64_t o = 0;
+    w.scale_bytes = align256((int64_t)sizeof(TileScale) * c->sp.max_items);
     w.off_states = o; o += plan.slots * w.state_bytes;
     w.off_final = o; o += w.state_bytes;
+    w.off_scales = o; o += (plan.slots + 1) * w.scale_bytes;  // slot s, then the final state
     w.off_lam = o; o += 2 * w.lam_bytes;
     w.off_nadj = o; o = align256(o + 16 * w.nodes);
     w.off_acc = o; o = align256(o + 8 * ADJ_ACC_DOUBLES + 4 * 8 * ADJ_SLOTS);
@@ -535,9 +553,18 @@ struct AdjRun {
     std::map<int64_t, int> saved;  // step -> slot, states kept by the forward pass
     float *lam_cur = nullptr, *lam_nxt = nullptr;
     int64_t recomputed = 0, live = 0, max_live = 0;
+    // State buffers 0 .. slots-1, and `fin` (= slots) for s_T.  Each holds
+    // the packed state and, when the fused kernel stored that state, the
+    // P2G tile scales it recorded (valid), so that a P2G of the saved state
+    // reproduces the forward pass's grid bit for bit.
+    int fin = 0;
+    std::vector<char> valid;
 
-    uint32_t *slot_ptr(int s) { return reinterpret_cast<uint32_t *>(ws + w.off_states + (int64_t)s * w.state_bytes); }
-    uint32_t *final_ptr() { return reinterpret_cast<uint32_t *>(ws + w.off_final); }
+    uint32_t *slot_ptr(int s) {
+        return reinterpret_cast<uint32_t *>(ws + (s == fin ? w.off_final : w.off_states + (int64_t)s * w.state_bytes));
+    }
+    TileScale *scale_ptr(int s) { return reinterpret_cast<TileScale *>(ws + w.off_scales + (int64_t)s * w.scale_bytes); }
+    int64_t scale_words() const { return (int64_t)sizeof(TileScale) / 4 * c->sp.max_items; }
     double *acc() { return reinterpret_cast<double *>(ws + w.off_acc); }
     uint32_t *rng() { return reinterpret_cast<uint32_t *>(ws + w.off_acc + 8 * ADJ_ACC_DOUBLES); }
     float4 *nadj() { return reinterpret_cast<float4 *>(ws + w.off_nadj); }
@@ -553,14 +580,29 @@ struct AdjRun {
         free_slots.push_back(s);
         --live;
     }
-    mpmq_status copy_state(const uint32_t *from, uint32_t *to) {
-        HIPCHK(c, launch_copy_u32(from, to, state_words(), c->stream), "adjoint: state copy");
+    // c->words (and its tile scales) into buffer s, and back
+    mpmq_status save(int s) {
+        HIPCHK(c, launch_copy_u32(c->words, slot_ptr(s), state_words(), c->stream), "adjoint: state copy");
+        if (c->scales_valid)
+            HIPCHK(c, launch_copy_u32(reinterpret_cast<const uint32_t *>(c->iscale()),
+                                      reinterpret_cast<uint32_t *>(scale_ptr(s)), scale_words(), c->stream),
+                   "adjoint: scale copy");
+        valid[(size_t)s] = c->scales_valid ? 1 : 0;
         return MPMQ_OK;
     }
-    // c->words = s_from (taken from `from`), then substeps up to each target
-    // step in ascending order, copying s_t into its slot.
-    mpmq_status advance(const uint32_t *from, int64_t t_from, const std::vector<std::pair<int64_t, int>> &targets) {
-        mpmq_status r = copy_state(from, c->words);
+    mpmq_status load(int s) {
+        HIPCHK(c, launch_copy_u32(slot_ptr(s), c->words, state_words(), c->stream), "adjoint: state copy");
+        if (valid[(size_t)s])
+            HIPCHK(c, launch_copy_u32(reinterpret_cast<const uint32_t *>(scale_ptr(s)),
+                                      reinterpret_cast<uint32_t *>(c->iscale()), scale_words(), c->stream),
+                   "adjoint: scale copy");
+        c->scales_valid = valid[(size_t)s] != 0;
+        return MPMQ_OK;
+    }
+    // c->words = s_from (taken from buffer `from`), then substeps up to each
+    // target step in ascending order, saving s_t into its buffer.
+    mpmq_status advance(int from, int64_t t_from, const std::vector<std::pair<int64_t, int>> &targets) {
+        mpmq_status r = load(from);
         if (r != MPMQ_OK) return r;
         if ((r = reset_grids(c)) != MPMQ_OK) return r;
         c->step = step0 + t_from;
@@ -571,17 +613,19 @@ struct AdjRun {
                 ++t;
                 ++recomputed;
             }
-            if ((r = copy_state(c->words, slot_ptr(tg.second))) != MPMQ_OK) return r;
+            if ((r = save(tg.second)) != MPMQ_OK) return r;
         }
         return MPMQ_OK;
     }
-    // lambda_t from lambda_{t+1} at stored state `words` (s_t).
-    mpmq_status adjoint_step(const uint32_t *words) {
+    // lambda_t from lambda_{t+1} at the state s_t held in buffer `slot`.
+    mpmq_status adjoint_step(int slot) {
         mpmq_status r = reset_grids(c);
         if (r != MPMQ_OK) return r;
         hipStream_t st = c->stream;
+        const uint32_t *words = slot_ptr(slot);
         HIPCHK(c, launch_p2g(c->dim, c->ds.mat, c->dscheme(), c->dp, words, c->cap_pad, c->items(), c->n_items(),
-                             c->launch_grid, c->grid[0], c->flags(0), c->stats(), st, c->jit_ptr()), "adjoint: p2g");
+                             c->launch_grid, c->grid[0], c->flags(0), valid[(size_t)slot] ? scale_ptr(slot) : nullptr,
+                             c->irec(), c->stats(), st, c->jit_ptr()), "adjoint: p2g");
         HIPCHK(c, launch_grid_update(c->dim, c->dp, c->grid[0], c->grid[1], c->flags(0), c->flags(1), c->sp.nblocks,
                                      c->stats(), st), "adjoint: grid update");
         {
@@ -597,7 +641,7 @@ struct AdjRun {
     // Reverses steps [lo, hi) given s_lo in slot `slot_lo` and lambda_hi in
     // lam_cur; leaves lambda_lo in lam_cur.
     mpmq_status reverse_bisect(int64_t lo, int64_t hi, int slot_lo) {
-        if (hi - lo == 1) return adjoint_step(slot_ptr(slot_lo));
+        if (hi - lo == 1) return adjoint_step(slot_lo);
         const int64_t mid = (lo + hi) / 2;
         int slot_mid;
         mpmq_status r;
@@ -607,7 +651,7 @@ struct AdjRun {
             saved.erase(it);
         } else {
             slot_mid = take();
-            if ((r = advance(slot_ptr(slot_lo), lo, {{mid, slot_mid}})) != MPMQ_OK) return r;
+            if ((r = advance(slot_lo, lo, {{mid, slot_mid}})) != MPMQ_OK) return r;
         }
         if ((r = reverse_bisect(mid, hi, slot_mid)) != MPMQ_OK) return r;
         give(slot_mid);
@@ -619,13 +663,13 @@ struct AdjRun {
         std::vector<std::pair<int64_t, int>> tg;
         for (int64_t t = a + 1; t < b; ++t) tg.push_back({t, take()});
         mpmq_status r;
-        if (!tg.empty() && (r = advance(slot_ptr(slot_a), a, tg)) != MPMQ_OK) return r;
+        if (!tg.empty() && (r = advance(slot_a, a, tg)) != MPMQ_OK) return r;
         for (int64_t t = b - 1; t > a; --t) {
             const int s = tg[(size_t)(t - a - 1)].second;
-            if ((r = adjoint_step(slot_ptr(s))) != MPMQ_OK) return r;
+            if ((r = adjoint_step(s)) != MPMQ_OK) return r;
             give(s);
         }
-        return adjoint_step(slot_ptr(slot_a));
+        return adjoint_step(slot_a);
     }
 };
 
@@ -719,6 +763,8 @@ mpmq_status mpmq_create(const mpmq_scheme *scheme, const mpmq_params *params, co
     bd.flags[0] = c->flags(0);
     bd.flags[1] = c->flags(1);
     bd.stats = c->stats();
+    bd.iscale = c->iscale();
+    bd.irec = c->irec();
     bd.nblocks = c->sp.nblocks;
     bd.P = c->dp;
     if (e == hipSuccess) e = hipMemcpyAsync(c->scratch + c->sp.batch, &bd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream);
@@ -754,6 +800,7 @@ mpmq_status mpmq_encode(mpmq_ctx *c, const float *x, const float *v, const float
     c->n = n;
     c->encoded = true;
     c->sorted = false;
+    c->scales_valid = false;
     return MPMQ_OK;
 }
 
@@ -846,6 +893,7 @@ mpmq_status mpmq_stats(mpmq_ctx *c, mpmq_stats_t *out) {
     out->fallback = (int64_t)h[ST_FALLBACK];
     out->clamped = (int64_t)h[ST_CLAMP];
     out->atomics = (int64_t)h[ST_ATOMICS];
+    out->wide = (int64_t)h[ST_WIDE];
     out->active_nodes = 0;
     for (int i = 0; i < ST_ACTIVE_SLOTS; ++i) out->active_nodes += (int64_t)h[ST_ACTIVE + i];
     return MPMQ_OK;
@@ -876,6 +924,11 @@ mpmq_status mpmq_specialize(mpmq_ctx *c, int32_t enable) {
     JitKernels k{};
     if (!jit_kernels(c->dim, c->ds, c->dp, c->cap_pad, &k, &err)) return fail(c, MPMQ_EDEVICE, "specialize: " + err);
     c->jit = k;
+    // the generic fused kernel keeps no item records: until the next P2G
+    // outside it, the specialized one starts from "no record" (-1)
+    if (!c->use_jit)
+        HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(c->irec()), 0xbf800000u, 4 * c->sp.max_items, c->stream),
+               "specialize: records");
     c->use_jit = true;
     return MPMQ_OK;
 }
@@ -953,6 +1006,8 @@ mpmq_status adjoint_impl(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
     run.lam_cur = reinterpret_cast<float *>(run.ws + run.w.off_lam);
     run.lam_nxt = reinterpret_cast<float *>(run.ws + run.w.off_lam + run.w.lam_bytes);
     for (int s = (int)plan.slots - 1; s >= 0; --s) run.free_slots.push_back(s);
+    run.fin = (int)plan.slots;
+    run.valid.assign((size_t)plan.slots + 1, 0);
     HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t *>(run.acc()), 0u, 2 * ADJ_ACC_DOUBLES, st), "adjoint: clear");
     HIPCHK(c, launch_fill_u32(run.rng(), 0xffffffffu, 4 * ADJ_SLOTS, st), "adjoint: clear");
     HIPCHK(c, launch_fill_u32(run.rng() + 4 * ADJ_SLOTS, 0u, 4 * ADJ_SLOTS, st), "adjoint: clear");
@@ -972,7 +1027,7 @@ mpmq_status adjoint_impl(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
         HIPCHK(c, launch_adj_range(c->dim, c->ds.mat, c->dscheme(), c->words, c->cap_pad, n, run.rng(), st), "adjoint: ranges");
         if (save_i < plan.forward_saves.size() && plan.forward_saves[save_i] == t) {
             const int s = run.take();
-            if ((r = run.copy_state(c->words, run.slot_ptr(s))) != MPMQ_OK) return r;
+            if ((r = run.save(s)) != MPMQ_OK) return r;
             run.saved[t] = s;
             ++save_i;
         }
@@ -981,7 +1036,7 @@ mpmq_status adjoint_impl(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
     const int64_t steps_after = c->steps_taken;
     HIPCHK(c, launch_copy_u32(reinterpret_cast<uint32_t *>(c->stats()), reinterpret_cast<uint32_t *>(run.ws + run.w.off_stats),
                               2 * ST_COUNT, st), "adjoint: stats");
-    if ((r = run.copy_state(c->words, run.final_ptr())) != MPMQ_OK) return r;
+    if ((r = run.save(run.fin)) != MPMQ_OK) return r;
     // objective at s_T and lambda_T
     HIPCHK(c, launch_adj_objective(c->dim, c->ds.mat, c->dscheme(), c->dp, c->words, c->cap_pad, n, spec->objective, spec->axis,
                                    run.lam_cur, run.acc(), st), "adjoint: objective");
@@ -1014,8 +1069,8 @@ mpmq_status adjoint_impl(mpmq_ctx *c, const mpmq_adjoint_spec *spec, void *works
         }
     }
     // restore s_T, the step counter and the statistics of the forward pass
-    if ((r = run.copy_state(run.final_ptr(), c->words)) != MPMQ_OK) return r;
-    if ((r = reset_grids(c)) != MPMQ_OK) return r;
+    if ((r = run.load(run.fin)) != MPMQ_OK) return r;
+    if ((r = reset_grids(c)) != MPMQ_OK) return r;  // the next substep's P2G replays the recorded scales
     HIPCHK(c, launch_copy_u32(reinterpret_cast<uint32_t *>(run.ws + run.w.off_stats), reinterpret_cast<uint32_t *>(c->stats()),
                               2 * ST_COUNT, st), "adjoint: stats");
     c->step = run.step0 + T;
