@@ -544,11 +544,14 @@ __device__ __forceinline__ float4 item_record(const float *red, const volatile f
 // Scales of the 32-bit node tile of a work item of n particles (see
 // TileScale) from the item's record of its last P2G (rec, see item_record):
 // vref is v0 rounded to a multiple of 2^-(32 - sm), and s the largest
-// exponent at which 1.25 x the recorded bound (a quarter for growth, plus
-// the rounding of vref and a floor) fits under lim.  Only the precision
-// depends on this estimate: admission to the tile is checked per particle.
+// exponent at which the expected deviation fits under lim: 1.25 x the
+// recorded bound (a quarter for growth) plus the rounding of vref, plus a
+// floor for an item that moved uniformly at its last P2G (the record is then
+// about zero, while this substep adds gravity, dvg = dt |g|, and the
+// velocity's quantization, here 2^-6 |vref|).  Only the precision depends
+// on this estimate: admission to the tile is checked per particle.
 template <int DIM>
-__device__ __forceinline__ TileScale tile_scale(int n, float4 rec) {
+__device__ __forceinline__ TileScale tile_scale(int n, float4 rec, float dvg) {
     // binary32 throughout: wb is exact (n <= 4096), the bounds 2^32 - 2^13
     // and 2^31 - 2^13 are exact, sm is checked after the rounded division,
     // and lim_v keeps a 2^-20 margin over the rounding of lim
@@ -572,7 +575,7 @@ __device__ __forceinline__ TileScale tile_scale(int n, float4 rec) {
         shift = fmaxf(shift, fabsf(v0[a] - vref[a]));
         mabs = fmaxf(mabs, fabsf(vref[a]));
     }
-    const float dev = known ? 1.25f * (rec.w + shift) + 0x1p-10f * mabs + 0x1p-16f : 1.0f + shift;
+    const float dev = known ? 1.25f * (rec.w + shift) + 0x1p-6f * mabs + dvg + 0x1p-12f : 1.0f + shift;
     const int sx = max(0, min(32, ilogbf(lim / dev)));
     TileScale ts;
     ts.s = uni(sx);
@@ -837,7 +840,8 @@ __device__ __forceinline__ void substep_items(const DevScheme *__restrict__ sch,
         __syncthreads();
         volatile TileScale &ts = tsw[threadIdx.x >> 6];  // the wave's own copy
         if (T32 && tiled && do_p2g) {
-            const TileScale t = tile_scale<DIM>(it.p1 - it.p0, irec[item]);
+            const float dvg = P.dt * fmaxf(fmaxf(fabsf(P.g[0]), fabsf(P.g[1])), fabsf(P.g[2]));
+            const TileScale t = tile_scale<DIM>(it.p1 - it.p0, irec[item], dvg);
             if (__lane_id() == 0) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) ts.vref[a] = t.vref[a];
