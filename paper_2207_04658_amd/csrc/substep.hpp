@@ -1,9 +1,10 @@
 // substep.hpp -- gfx950 device code of the fused substep and of the
-// bootstrap P2G: exact fixed-point P2G into an LDS node tile, G2P from the
-// tile, the per-particle update, the dithered encode and store.  Compiled
-// into libmpmq.so for any scheme read at run time, and (when a context asks
-// for it) compiled again at run time with the context's scheme as a
-// compile-time constant.
+// bootstrap P2G: integer fixed-point P2G into an LDS node tile, G2P from
+// the tile, the per-particle update, the dithered encode and store.
+// Compiled into libmpmq.so for any scheme read at run time (64-bit node
+// tile), and (when a context asks for it) compiled again at run time with
+// the context's scheme as a compile-time constant (32-bit node tile at
+// per-item scales, three work-groups per CU).
 #pragma once
 #include "mpmq_device.hpp"
 
@@ -119,7 +120,8 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
 }
 
 // ---------------------------------------------------------------------------
-// Node tile of the fused kernel: 32-bit sums at a per-work-item scale.
+// Node tile of the scheme-specialized fused kernel: 32-bit sums at a
+// per-work-item scale (the generic build keeps the exact 64-bit tile).
 //
 // A work item's particles add, per node, w_i (v + (A/m)(x_i - x_p) - vref)
 // in units of 2^-s (three momentum sums) and w_i in units of 2^-sm (the
@@ -133,17 +135,17 @@ __device__ __forceinline__ void p2g_global(const DevParams &P, const int *base, 
 // values lie within lim 2^-s of vref with lim Wb < 2^31 (and its weights are
 // B-spline weights, 0.5 <= f <= 1.5).  Then no node sum leaves the 32-bit
 // range, and the rest go through the global 64-bit path (counted, ST_WIDE).
-// s is the largest exponent at which an item-typical deviation D (from the
-// spread of the item's node velocities, see tile_scale) fits under lim.
+// s is the largest exponent at which the deviation the item's record of its
+// last P2G predicts fits under lim (tile_scale, item_record).
 // ---------------------------------------------------------------------------
 
 // P2G of one particle from its decoded (quantized) state.  Node i receives,
 // per unit particle mass, w_i (v + (A/m)(x_i - x_p)) and w_i (Eq. 1 with
-// the MLS-MPM affine momentum), accumulated as exact fixed point: in the
-// bootstrap P2G (AccT = unsigned long long) as 64-bit sums at 2^-32 (raw
-// terms, see fixr; the offset comes off at the flush), in the fused kernel
-// (AccT = uint32_t) as the 32-bit tile above.  Stencils outside the tile go
-// to the grid directly (p2g_global).
+// the MLS-MPM affine momentum), accumulated as exact fixed point: with
+// AccT = unsigned long long as 64-bit sums at 2^-32 (raw terms, see fixr;
+// the offset comes off at the flush), with AccT = uint32_t in the 32-bit
+// tile above (the specialized fused kernel, and k_p2g replaying its
+// scales).  Stencils outside the tile go to the grid directly (p2g_global).
 // OUTLINE: the polar decomposition's rare SVD branch as a call (see polar3).
 template <int DIM, int MAT, bool OUTLINE, typename AccT>
 __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *xd, const float *v,
