@@ -194,14 +194,17 @@ mpmq_status mpmq_packed(mpmq_ctx *ctx, const uint32_t **words, int32_t *W, int64
 mpmq_status mpmq_step(mpmq_ctx *ctx, int32_t n_substeps);
 
 /* Batched substeps for serving many scenes: advances every context of
- * ctxs[0..count) by n_substeps, each exactly as mpmq_step would (same
- * results bit for bit: each scene keeps its own scheme, parameters, buffers,
- * step counter and Philox key), but with the grid update and the fused
+ * ctxs[0..count) by n_substeps, each exactly as mpmq_step with the generic
+ * kernels would (same results bit for bit: each scene keeps its own scheme,
+ * parameters, buffers, step counter and Philox key), but with the grid
+ * update and the fused
  * substep of all scenes issued as one launch each per substep (per chunk of
  * up to 96 scenes; sorts and the P2G after a sort stay per scene).  The
  * contexts must share the dimension, the material and the stream (the
  * launches go to that stream), and each may appear once.  Scheme-specialized
- * kernels (mpmq_specialize) are not used here.  Asynchronous.  EINVAL (NULL,
+ * kernels (mpmq_specialize) are not used here: a specialized context stepped
+ * in a batch follows the generic kernels' 64-bit P2G tile for those
+ * substeps.  Asynchronous.  EINVAL (NULL,
  * count < 1, mixed dimension / material / stream, duplicates), ESTATE
  * (a context before its first encode), EDEVICE; the message of any error is
  * mpmq_last_error(ctxs[0]) (of mpmq_last_error(NULL) when ctxs[0] is NULL). */
