@@ -271,33 +271,34 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
     constexpr int NC = ncomp<DIM, FID>(), K0 = canon0<DIM, FID>();
     const int m1 = f->bits - 1;
     const double qmax = (double)f->mag_mask;
-    double M = 0.0;
+    // the largest magnitude, taken in T (T values convert to binary64
+    // exactly and in order; fmax ignores a NaN operand)
+    T Mt = (T)0;
     uint64_t nan_lanes = 0ull;  // lanes of the wave with a NaN component
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const double x = (double)val[c];
-        if (RS) ls.nan += (x == x) ? 0u : 1u << (8 * slot_of<FID>());
+        if (RS) ls.nan += (val[c] == val[c]) ? 0u : 1u << (8 * slot_of<FID>());
         else nan_lanes |= __ballot(!(val[c] == val[c]));
-        M = fmax(M, fabs(x));  // fmax ignores a NaN operand
+        Mt = fmax(Mt, fabs(val[c]));
     }
+    const double M = (double)Mt;
     int E;
     if (M == 0.0) E = f->emin;
     else if (isinf(M)) E = f->emax;
     else E = min(max(ilogb(M) + 1, f->emin), f->emax);
     // raise E while a magnitude rounds up to 2^(m-1) (at most once in exact
     // arithmetic; the loop keeps the definition literal); the rounded
-    // magnitudes of the last pass are the codes
-    double tq[NC], qq[NC];
+    // magnitudes of the last pass are the codes.  A NaN component gives a
+    // NaN: the maximum below ignores it and the clamp maps it to code 0.
+    double qq[NC];
     double qtop_end;
     for (;;) {
         double qtop = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            double x = (double)val[c];
-            x = fmax(fabs(x), 0.0);  // NaN -> 0
             const double h = f->dither ? dither_h(rnd, K0 + c) : XI_HALF;
-            tq[c] = ldexp(x, m1 - E);
-            qq[c] = floor(fma(h, XI_SCALE, tq[c]));
+            const double sv = fma(h, XI_SCALE, ldexp(fabs((double)val[c]), m1 - E));
+            qq[c] = floor(sv);
             qtop = fmax(qtop, qq[c]);
         }
         qtop_end = qtop;
@@ -319,16 +320,18 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const double t = tq[c];
-        const double q = qq[c];
         uint32_t qc;
         if (RS || __builtin_expect(slow, 0)) {
+            const double q = fmax(qq[c], 0.0);  // NaN -> 0
             const bool above = q > qmax;
-            qc = (uint32_t)fmin(q, qmax);  // q >= 0
+            qc = (uint32_t)fmin(q, qmax);
             ls.sat += above ? 1u << (8 * slot_of<FID>()) : 0u;
-            if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
+            if (RS) {
+                const double t = ldexp(fabs((double)val[c]), m1 - E);  // NaN: counted as rounded down
+                ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
+            }
         } else {
-            qc = (uint32_t)q;  // q <= qmax
+            qc = (uint32_t)qq[c];  // 0 <= q <= qmax
         }
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
         os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);
@@ -720,16 +723,18 @@ __device__ __forceinline__ void polar3(const float *F, float *R) {
         bad |= !ok;
         // hardware reciprocal (1 ulp): the iteration absorbs its error
         const float hid = ok ? 0.5f * __builtin_amdgcn_rcpf(det) : 0.0f;
-        float Rn[9] = {0.5f * R[0] + hid * c00, 0.5f * R[1] + hid * c01, 0.5f * R[2] + hid * c02,
-                       0.5f * R[3] + hid * c10, 0.5f * R[4] + hid * c11, 0.5f * R[5] + hid * c12,
-                       0.5f * R[6] + hid * c20, 0.5f * R[7] + hid * c21, 0.5f * R[8] + hid * c22};
+        // the Newton step d = (R^-T - R) / 2, added in place
+        const float cf[9] = {c00, c01, c02, c10, c11, c12, c20, c21, c22};
         d2 = 0.0f;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const float d = Rn[i] - R[i];
-            d2 += d * d;
-            R[i] = ok ? Rn[i] : ((i % 4 == 0) ? 1.0f : 0.0f);
+            const float d = fmaf(hid, cf[i], -0.5f * R[i]);
+            d2 = fmaf(d, d, d2);
+            R[i] += d;
         }
+        // a lane with a vanishing determinant takes the SVD below whatever
+        // its iterate (halved here, hid = 0): it no longer holds the loop
+        d2 = ok ? d2 : 0.0f;
         // Newton's polar iteration converges quadratically: the error of the
         // new iterate is about |R_new - R|^2 / (2 sigma_min), at most 5e-8
         // once the squared step is under 1e-7 (for sigma_min near 1): the

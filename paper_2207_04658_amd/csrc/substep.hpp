@@ -675,6 +675,19 @@ __global__ __launch_bounds__(PWG, PWG_WAVES_PER_EU) void k_p2g(const DevScheme *
 // fused substep: G2P -> update -> dithered encode + store -> P2G (next step)
 // ---------------------------------------------------------------------------
 
+// &p[i] as an opaque LDS address (p must point into LDS).  The G2P reads
+// below take a base per component and stencil plane (or row, in 2D) and
+// small constant offsets from it, which the paired LDS reads (ds_read2,
+// offsets up to 255 words) reach from that one register; with the whole
+// address visible the compiler would fold the component and plane into each
+// pair's offset and, past 255 words, spend an address add per pair.
+typedef const __attribute__((address_space(3))) float lds_f32;
+__device__ __forceinline__ lds_f32 *lds_base(const float *p, int i) {
+    lds_f32 *b = (lds_f32 *)p + i;
+    asm volatile("" : "+v"(b));
+    return b;
+}
+
 // G2P from the LDS tile, separable in the three axes:
 // v' = sum_i w v_i and S_b = sum_i w (o_b - f_b) v_i, C' = 4/dx S, computed as
 // S_b = sum_i w o_b v_i - f_b v' (o_b in {0, 1, 2}: the o_b = 0 terms drop out).
@@ -693,15 +706,17 @@ __device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, c
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
             float P00[3] = {0.f, 0.f, 0.f}, P01[3] = {0.f, 0.f, 0.f}, P10[3] = {0.f, 0.f, 0.f};
+            lds_f32 *bz[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) bz[a] = lds_base(gv, a * TN + l0 + oz * TB * TB);
 #pragma unroll
             for (int oy = 0; oy < 3; ++oy) {
                 float R0[3] = {0.f, 0.f, 0.f}, R1[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ox = 0; ox < 3; ++ox) {
-                    const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const float vi = gv[a * TN + idx];
+                        const float vi = bz[a][oy * TB + ox];
                         R0[a] += wx[0][ox] * vi;
                         if (ox > 0) R1[a] += wo[0][ox] * vi;
                     }
@@ -722,15 +737,17 @@ __device__ __forceinline__ void g2p_tile(const float *__restrict__ gv, int l0, c
             }
         }
     } else {
+        lds_f32 *bz[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) bz[a] = lds_base(gv, a * TN + l0);
 #pragma unroll
         for (int oy = 0; oy < 3; ++oy) {
             float R0[2] = {0.f, 0.f}, R1[2] = {0.f, 0.f};
 #pragma unroll
             for (int ox = 0; ox < 3; ++ox) {
-                const int idx = l0 + oy * TB + ox;
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    const float vi = gv[a * TN + idx];
+                    const float vi = bz[a][oy * TB + ox];
                     R0[a] += wx[0][ox] * vi;
                     if (ox > 0) R1[a] += wo[0][ox] * vi;
                 }
