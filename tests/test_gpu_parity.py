@@ -289,3 +289,63 @@ def test_p2g_clamp_is_counted(gpu_lib):
     ctx.step(1)
     assert ctx.stats()["clamped"] == 10
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["generic", "specialized", "stats"])
+def test_nan_position_substep(gpu_lib, orc, mode):
+    """A NaN position (stored raw) gives NaN B-spline weights, so G2P hands
+    the encoder NaN velocity, affine and deformation components: the
+    shared-exponent fields v and C and the fixed-point F store code 0 for
+    each and count it (Eq. 11; E from the finite components, here none), on
+    the generic and the scheme-specialized fused kernels and with the
+    round-up/down counters on.  A NaN position clamps to stencil base 0, so
+    the NaN particles touch only the grid corner, far from the others, which
+    are compared at the usual bars."""
+    rng = np.random.default_rng(17)
+    n = 3000
+    x, v, C, F = WL.random_state(rng, 3, n, x_lo=0.3, x_hi=0.7)
+    nan_ids = np.array([5, 100, 1777, 2999])
+    x[1, nan_ids] = np.nan
+    scheme = {"dim": 3, "seed": 9, "fields": [WL.raw("x"), WL.shared_exp("v", 13, 6, 20.0, True),
+                                              WL.shared_exp("C", 16, 6, 2048.0, True),
+                                              WL.fixed("F", 14, -1.0, 1.0, True, rel_identity=True)]}
+    sc = {"scheme": scheme, "params": WL.params(3, 64, 1e-4, 1e-6), "state": (x, v, C, F)}
+    note(f"NaN positions n={n} mode={mode}")
+    ctx = gpu_context(gpu_lib, sc)
+    if mode == "specialized":
+        ctx.specialize(True)
+    if mode == "stats":
+        ctx.set_stats(1)
+    sim, ow0, _ = oracle_sim(orc, sc)
+    ctx.reset_stats()
+    ctx.step(1)
+    sim.step(1)
+    gw, gids, ow, oids = ctx.words(), ctx.ids(), sim.words(), sim.ids()
+    g = [by_id(a, gids) for a in orc.decode(scheme, gw)]
+    o = [by_id(a, oids) for a in orc.decode(scheme, ow)]
+    # the NaN particles: position NaN, v = C = 0 (code 0), F - I = lo (code 0)
+    f0 = np.full(9, -1.0)
+    f0[[0, 4, 8]] = 0.0
+    for side in (g, o):
+        assert np.all(np.isnan(side[0][:, nan_ids]))
+        assert np.all(side[1][:, nan_ids] == 0.0) and np.all(side[2][:, nan_ids] == 0.0)
+        assert np.all(side[3][:, nan_ids] == f0[:, None])
+    # everyone else
+    keep = np.setdiff1d(np.arange(n), nan_ids)
+    dx, lsb = lsb_differences(orc, scheme, gw, gids, ow, oids, sc["params"], 1)
+    assert np.max(dx[:, keep]) <= 1e-4, np.max(dx[:, keep])
+    for f in "vCF":
+        d = lsb[f][:, keep]
+        assert np.mean(d <= 1 + 1e-9) >= 0.99 and np.max(d) <= 8, (f, np.max(d))
+    # counters: one NaN per component of each NaN particle, as the oracle counts
+    gst, ost = ctx.stats(), sim.stats()
+    for f, nc in (("v", 3), ("C", 9), ("F", 9)):
+        assert gst[f]["nan"] == ost[f]["nan"] == nc * len(nan_ids), (f, gst[f]["nan"], ost[f]["nan"])
+        assert gst[f]["sat"] == ost[f]["sat"], f
+    if mode == "stats":
+        for f in "vCF":
+            tot_g = gst[f]["up"] + gst[f]["down"]
+            tot_o = ost[f]["up"] + ost[f]["down"]
+            assert tot_g == tot_o, (f, tot_g, tot_o)
+    ctx.close()
+    sim.close()
