@@ -271,34 +271,33 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
     constexpr int NC = ncomp<DIM, FID>(), K0 = canon0<DIM, FID>();
     const int m1 = f->bits - 1;
     const double qmax = (double)f->mag_mask;
-    // the largest magnitude, taken in T (T values convert to binary64
-    // exactly and in order; fmax ignores a NaN operand)
-    T Mt = (T)0;
+    double M = 0.0;
     uint64_t nan_lanes = 0ull;  // lanes of the wave with a NaN component
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (RS) ls.nan += (val[c] == val[c]) ? 0u : 1u << (8 * slot_of<FID>());
+        const double x = (double)val[c];
+        if (RS) ls.nan += (x == x) ? 0u : 1u << (8 * slot_of<FID>());
         else nan_lanes |= __ballot(!(val[c] == val[c]));
-        Mt = fmax(Mt, fabs(val[c]));
+        M = fmax(M, fabs(x));  // fmax ignores a NaN operand
     }
-    const double M = (double)Mt;
     int E;
     if (M == 0.0) E = f->emin;
     else if (isinf(M)) E = f->emax;
     else E = min(max(ilogb(M) + 1, f->emin), f->emax);
     // raise E while a magnitude rounds up to 2^(m-1) (at most once in exact
     // arithmetic; the loop keeps the definition literal); the rounded
-    // magnitudes of the last pass are the codes.  A NaN component gives a
-    // NaN: the maximum below ignores it and the clamp maps it to code 0.
-    double qq[NC];
+    // magnitudes of the last pass are the codes
+    double tq[NC], qq[NC];
     double qtop_end;
     for (;;) {
         double qtop = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
+            double x = (double)val[c];
+            x = fmax(fabs(x), 0.0);  // NaN -> 0
             const double h = f->dither ? dither_h(rnd, K0 + c) : XI_HALF;
-            const double sv = fma(h, XI_SCALE, ldexp(fabs((double)val[c]), m1 - E));
-            qq[c] = floor(sv);
+            tq[c] = ldexp(x, m1 - E);
+            qq[c] = floor(fma(h, XI_SCALE, tq[c]));
             qtop = fmax(qtop, qq[c]);
         }
         qtop_end = qtop;
@@ -320,18 +319,16 @@ __device__ __forceinline__ void enc_sexp(const FieldRef f, const T *val, Draws &
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+        const double t = tq[c];
+        const double q = qq[c];
         uint32_t qc;
         if (RS || __builtin_expect(slow, 0)) {
-            const double q = fmax(qq[c], 0.0);  // NaN -> 0
             const bool above = q > qmax;
-            qc = (uint32_t)fmin(q, qmax);
+            qc = (uint32_t)fmin(q, qmax);  // q >= 0
             ls.sat += above ? 1u << (8 * slot_of<FID>()) : 0u;
-            if (RS) {
-                const double t = ldexp(fabs((double)val[c]), m1 - E);  // NaN: counted as rounded down
-                ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
-            }
+            if (RS) ls.ud[slot_of<FID>()] += above ? 0u : (q > floor(t)) ? 1u : 0x10000u;
         } else {
-            qc = (uint32_t)qq[c];  // 0 <= q <= qmax
+            qc = (uint32_t)q;  // q <= qmax
         }
         const bool neg = (double)val[c] < 0.0 && qc > 0u;
         os.emit(qc | ((neg ? 1u : 0u) << m1), f->bits);

@@ -274,6 +274,14 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
         const int ex = T32 ? ts.s - 32 : 0, sw = T32 ? ts.sm : 32;
         // node values stepped along each axis (q + sum_b a_b o_b by additions)
         if constexpr (DIM == 3) {
+            // x weights at the two scales (exact: powers of two); a term's
+            // weight is then w_z w_y (exact in binary64) times one of them
+            double wxs[3], wxm[3];
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                wxs[ox] = ldexp(w[0][ox], ex);
+                wxm[ox] = ldexp(w[0][ox], sw);
+            }
             double vz[3] = {q[0], q[1], q[2]};
 #pragma unroll
             for (int oz = 0; oz < 3; ++oz) {
@@ -287,18 +295,17 @@ __device__ __forceinline__ void p2g_particle(const DevParams &P, const double *x
 #pragma unroll
                         for (int a = 0; a < 3; ++a) vzy[a] += ac[1][a];
                     const double wzy = w[2][oz] * w[1][oy];
-                    const double ms = ldexp(wzy, sw), wzs = ldexp(wzy, ex);  // exact (powers of two)
                     double val[3] = {vzy[0], vzy[1], vzy[2]};
 #pragma unroll
                     for (int ox = 0; ox < 3; ++ox) {
                         if (ox > 0)
 #pragma unroll
                             for (int a = 0; a < 3; ++a) val[a] += ac[0][a];
-                        const double wt = wzs * w[0][ox];
+                        const double wt = wzy * wxs[ox];
                         const int idx = l0 + (oz * TB + oy) * TB + ox;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) atomicAdd(&acc[a * TS + idx], (AccT)fixr(wt, val[a]));
-                        atomicAdd(&acc[3 * TS + idx], (AccT)fixr(w[0][ox], ms));
+                        atomicAdd(&acc[3 * TS + idx], (AccT)fixr(wxm[ox], wzy));
                     }
                 }
             }
