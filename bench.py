@@ -42,10 +42,14 @@ def log(msg):
 
 
 def kernel_hash():
+    """Hash of what the fused kernel is compiled from: its sources and the
+    device flags that the build hands to the compiler (and to hipRTC)."""
+    from paper_2207_04658_amd import build as _build
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(_build.DEVICE_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
